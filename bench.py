@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the sum-factorized IGA hot path on one MI355X.
+
+Default workload: d = 3, 48^3 elements, order p = 4, perturbed-Greville
+geometry, a(x) = 1 + 0.5 sin(2 pi x1) sin(2 pi x2) sin(2 pi x3), stiffness,
+FP64.  One step = the whole hot path on inputs resident in HBM:
+  geometry step (Jacobian, inverse, determinant folded into the coefficient
+  tensor) -> CSR pattern -> global sum-factorized assembly -> one
+  matrix-free apply y = K x.
+The 1D tables are built once at patch creation (host, cost sum p^2 #X) and
+reported separately.
+
+Prints one JSON line.  ``value`` is the assembly throughput of the whole
+step: nnz / step time, in Gnnz/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "matrix-free apply GDoF/s + assembly Gnnz/s, mixed vs FP64 at stated rel. error"
+PEAK_FP64_TFLOPS = 78.6          # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
+PEAK_HBM_GBS = 8000.0
+
+
+def nnz1(N, p):
+    return N * (2 * p - 1) - p * (p - 1)
+
+
+def assembly_flops(K, p, op):
+    """Algorithmic flops of Algorithm 1 with exact band sizes (eq. (sum
+    factorization-nnz)): level i costs p^2 (prod_{l>=i} #X_l) nnz(A^{i-1})
+    per (test, trial) pair; stiffness pairs are grouped as the kernel does
+    (9 pairs at levels 1-2, 4 groups at level 3)."""
+    Q = [k * p for k in K]
+    N = [k + p - 1 for k in K]
+    npair, ngroup = (9, 4) if op == "stiff" else (1, 1)
+    fma = (npair * Q[2] * Q[1] * Q[0] * p * p
+           + npair * Q[2] * Q[1] * p * p * nnz1(N[0], p)
+           + ngroup * Q[2] * p * p * nnz1(N[0], p) * nnz1(N[1], p))
+    return 2 * fma
+
+
+def apply_flops(K, p, op):
+    """Sum-factorized apply (Algorithms 3 and 2): forward contractions
+    3 -> 2 -> 1, pointwise 3x3 product, backward 1 -> 2 -> 3."""
+    Q = [k * p for k in K]
+    N = [k + p - 1 for k in K]
+    if op == "stiff":
+        fwd = 2 * p * (2 * Q[2] * N[1] * N[0] + 3 * Q[2] * Q[1] * N[0] + 3 * Q[2] * Q[1] * Q[0])
+        return 2 * fwd + 2 * 9 * Q[0] * Q[1] * Q[2]
+    fwd = 2 * p * (Q[2] * N[1] * N[0] + Q[2] * Q[1] * N[0] + Q[2] * Q[1] * Q[0])
+    return 2 * fwd + 2 * Q[0] * Q[1] * Q[2]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--elements", type=int, default=48)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--cpu-sample-elements", type=int, default=32,
+                    help="elements per direction of the patch the oracle assembles for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    prec = sf.SF_FP64 if args.prec == "fp64" else sf.SF_FP32
+    K = (args.elements,) * 3
+    p = args.order
+    w = inputs.workload_3d(K, p)
+    stream = torch.cuda.current_stream()
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    t_tab = time.perf_counter()
+    h = sf.sf_patch_create(ctx, 3, p, w["knots"], w["ctrl"])
+    t_tab = time.perf_counter() - t_tab
+    N, nnz, Q = sf.sf_patch_info(h)
+    sf.sf_patch_set_coef(ctx, h, sf.SF_STIFF, sf.SF_COEF_SINPROD, 0.5)
+    rp = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+    ci = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    x = torch.as_tensor(w["x"]).cuda()
+    y = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    stage_ms = np.zeros(4)
+
+    def step(record):
+        if record:
+            ev[0].record(stream)
+        sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, prec)
+        if record:
+            ev[1].record(stream)
+        sf.sf_csr_pattern(ctx, h, rp, ci)
+        if record:
+            ev[2].record(stream)
+        sf.sf_assemble(ctx, h, sf.SF_STIFF, prec, val_stiff=vals)
+        if record:
+            ev[3].record(stream)
+        sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
+        if record:
+            ev[4].record(stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        # per-stage durations from HIP events on the library's stream
+        ev[4].synchronize()
+        stage_ms += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    stage_ms /= args.steps
+    geom_ms, pat_ms, asm_ms, app_ms = stage_ms.tolist()
+
+    fl_asm = assembly_flops(K, p, "stiff")
+    fl_app = apply_flops(K, p, "stiff")
+    esz = 8 if prec == sf.SF_FP64 else 4
+    c_bytes = 6 * Q * esz
+    asm_bytes = c_bytes + nnz * 8
+    app_bytes = c_bytes + 2 * N * 8
+    asm_tflops = fl_asm / (asm_ms * 1e-3) / 1e12
+    roofline = {"kernel": "asm3d_kernel (Algorithm 1, levels 1-3)", "bound": "alu", "achieved": asm_tflops,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": asm_tflops / PEAK_FP64_TFLOPS,
+                "traffic": None,
+                "algorithmic_flops": fl_asm, "algorithmic_bytes": asm_bytes,
+                "achieved_GBs": asm_bytes / (asm_ms * 1e-3) / 1e9}
+    out = {
+        "metric": METRIC,
+        "value": nnz / (ms_per_step * 1e-3) / 1e9,
+        "unit": "Gnnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_assembly_plus_apply",
+                   "d": 3, "elements": list(K), "order": p, "ndof": N, "nnz": nnz, "nquad": Q,
+                   "coefficient": "1+0.5*sin(2pi x1)sin(2pi x2)sin(2pi x3)", "precision": args.prec},
+        "stages_ms": {"geometry": geom_ms, "pattern": pat_ms, "assembly": asm_ms, "apply": app_ms,
+                      "tables_host_once": t_tab * 1e3},
+        "assembly_gnnz_s": nnz / (asm_ms * 1e-3) / 1e9,
+        "apply_gdof_s": N / (app_ms * 1e-3) / 1e9,
+        "apply_hbm_frac": app_bytes / (app_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "apply_tflops": fl_app / (app_ms * 1e-3) / 1e12,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        out.update(cpu_leg(args, w, h, ctx, rp, ci, vals, y, K, p, prec))
+    sf.sf_patch_destroy(h)
+    sf.sf_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_leg(args, w, h, ctx, rp, ci, vals, y, K, p, prec):
+    """Oracle leg: error of the GPU results on sampled rows, and the oracle's
+    own throughput on a bounded sample of the same recipe."""
+    import torch
+
+    import oracle
+    from paper_1809_05471_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    torch.cuda.synchronize()
+    P = oracle.Problem(w["knots"], p, w["ctrl"], w["coef"])
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, P.N // 2, P.N - 1], rng.integers(0, P.N, 29)]))
+    rpn = rp.cpu().numpy()
+    vn = vals.cpu().numpy()
+    yn = y.cpu().numpy()
+    ref = P.rows(oracle.STIFF, rows, threads)
+    vmax = max(np.abs(v).max() for _, v in ref)
+    eA = max(np.abs(vn[rpn[r]:rpn[r + 1]] - v).max() for r, (_, v) in zip(rows, ref)) / vmax
+    yo = P.apply_rows(oracle.STIFF, w["x"], rows, threads)
+    scale = max(np.abs(v) @ np.abs(w["x"][c]) for c, v in ref)
+    ey = np.abs(yn[rows] - yo).max() / scale
+
+    ks = args.cpu_sample_elements
+    ws = inputs.workload_3d((ks, ks, ks), p)
+    Ps = oracle.Problem(ws["knots"], p, ws["ctrl"], ws["coef"])
+    pat = Ps.pattern()
+    t0 = time.perf_counter()
+    Ps.assemble(oracle.STIFF, threads, pattern=pat)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ps.apply(oracle.STIFF, ws["x"], threads)
+    t_app = time.perf_counter() - t0
+    nnz_s = len(pat[1])
+    return {
+        "err_A": float(eA), "err_y": float(ey), "err_rows_sampled": int(len(rows)),
+        "cpu_baseline": {"value": nnz_s / t_asm / 1e9, "unit": "Gnnz/s", "cores": threads, "kind": "oracle",
+                         "sample": f"oracle element-by-element stiffness assembly (cost N p^3d) of the "
+                                   f"{ks}^3-element order-{p} patch of the same recipe, nnz={nnz_s}, "
+                                   f"{t_asm:.2f} s; matrix-free apply of it {t_app:.2f} s",
+                         "apply_gdof_s": Ps.N / t_app / 1e9,
+                         "seconds": t_asm + t_app},
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * sfiga.h - sum-factorized isogeometric assembly and matrix-free apply on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows Bressan & Takacs, "Sum factorization
+ * techniques in Isogeometric Analysis":
+ *   - tensor-product B-spline bases of order p (= degree + 1) over open knot
+ *     vectors, one per direction (Sec. 3.1, eq. (prelim-tp); Corollary on
+ *     #NZ for open knot vectors in Sec. 3.2);
+ *   - tensor-product Gauss quadrature with p points per element and
+ *     direction (Sec. 3.2, Example "Gauss quadrature");
+ *   - a geometry map G = sum_n c_n phi_n given by control points (Sec. 6.3);
+ *   - the mass and stiffness forms of the convection-diffusion pull-back
+ *     (Sec. 2, Example 1), discretised as the quadrature sum
+ *     eq. (quadrature:1):
+ *        M[m][n] = sum_x w(x) c(G(x)) |det J| phi_n phi_m
+ *        K[m][n] = sum_x w(x) a(G(x)) |det J| (J^-T grad phi_n).(J^-T grad phi_m)
+ *     with J_ik = dG_i/dxhat_k;
+ *   - outputs: the matrix in CSR form (global sum factorization, Algorithm 1)
+ *     or the product y = A x (matrix-free, Algorithms 2 and 3).
+ *
+ * Index conventions (Sec. 3.1): all multi-indices are flattened
+ * lexicographically with direction 1 fastest, n = i1 + N1*(i2 + N2*i3).
+ * Rows are test functions m, columns trial functions n.  The CSR pattern is
+ * the structural one of Sec. 3.2 (pairs whose supports share an element),
+ * explicit zeros included, columns ascending; it is shared by the mass and
+ * stiffness matrices (Note after the definition of NZ).
+ *
+ * Supported: d = 1, 2, 3; one order p in 2..9 for all directions (apply and
+ * the geometry step), p in 2..6 for d = 3 assembly; open knot vectors with
+ * simple interior knots (maximal smoothness), any spacing.  Other inputs
+ * return SF_EUNSUPPORTED.
+ *
+ * Memory and streams.  Every pointer documented as "device" is HIP device
+ * memory owned by the caller (typically a torch tensor).  The library owns
+ * its internal workspace (1D tables, coefficient tensor, scratch) and frees
+ * it in the matching destroy call.  All work is enqueued on the context's
+ * stream and is asynchronous with respect to the host, except where a
+ * function is documented to synchronise.
+ *
+ * Errors.  Every function returns sf_status; no C++ exception crosses the
+ * ABI.  On error the outputs are unspecified, the handles stay valid and
+ * sf_last_error() describes the failure.  Handles are not thread safe: one
+ * host thread at a time per context.
+ */
+#ifndef SFIGA_H
+#define SFIGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SF_OK = 0,
+    SF_EINVAL = -1,        /* bad argument: NULL pointer, size or enum out of range */
+    SF_EKNOT = -2,         /* knot vector not open / not nondecreasing / too short */
+    SF_EGEOM = -3,         /* det J <= 0 at some quadrature point */
+    SF_ENOMEM = -4,        /* device allocation failed */
+    SF_EDEVICE = -5,       /* HIP runtime error */
+    SF_EUNSUPPORTED = -6   /* valid input outside the supported set listed above */
+} sf_status;
+
+typedef enum {
+    SF_FP64 = 0,           /* coefficient tensor and contractions in FP64 */
+    SF_FP32 = 1,           /* coefficient tensor and contractions in FP32, FP64 output */
+    SF_BF16_SPLIT = 2,     /* reserved: BF16 MFMA with hi/lo split correction */
+    SF_FP16_SPLIT = 3      /* reserved: FP16 MFMA with hi/lo split correction */
+} sf_precision;
+
+/* operator bit flags */
+enum { SF_MASS = 1u, SF_STIFF = 2u };
+
+typedef enum {
+    SF_COEF_CONST = 0,     /* params[0] = constant value */
+    SF_COEF_SINPROD = 1,   /* 1 + params[0] * prod_i sin(2 pi x_i), x = G(xhat) physical */
+    SF_COEF_QPVALUES = 2   /* values at the quadrature points, device [Q], lexicographic,
+                              quadrature direction 1 fastest (see sf_patch_quad_points) */
+} sf_coef_kind;
+
+typedef struct sf_ctx sf_ctx;
+typedef struct sf_patch sf_patch;
+typedef struct sf_batch sf_batch;
+
+/* ------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * borrowed from the caller (NULL = the legacy default stream); it must
+ * outlive the context.  *out receives the handle. */
+sf_status sf_ctx_create(int device, void *hip_stream, sf_ctx **out);
+
+/* Destroy a context.  All patches and batches created on it must have been
+ * destroyed first.  NULL is accepted. */
+void sf_ctx_destroy(sf_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none).  The string
+ * is owned by the context and valid until the next call on it. */
+const char *sf_last_error(const sf_ctx *ctx);
+
+/* Name of the device code object the library was built for ("gfx950"). */
+const char *sf_build_target(void);
+
+/* Host-only: the 1D tables the kernels use for one direction (Sec. 6.1),
+ * without a device.  Validates the knot vector like sf_patch_create and
+ * writes, for the K elements (K = n_knots - 2 order + 1), the Gauss points
+ * x[K][p], weights w[K][p] (p = order points per element) and the values and
+ * derivatives B[K][p][p], D[K][p][p] of the p active B-splines (element e
+ * activates functions e .. e+p-1).  Host pointers; any output may be NULL;
+ * *nel receives K.  Returns SF_EKNOT / SF_EUNSUPPORTED like sf_patch_create. */
+sf_status sf_host_tables_1d(const double *knots, int64_t n_knots, int order, int *nel, double *x, double *w,
+                            double *B, double *D);
+
+/* --------------------------------------------------------------- patch */
+
+/* One tensor-product patch: the inputs of Algorithms 1-3 in the IGA setting
+ * of Sec. 6.3.  knots[k] (host, n_knots[k] doubles) is the open knot vector
+ * of direction k+1; ctrl points to the control points c_n, [N][d] FP64,
+ * lexicographic with direction 1 fastest; ctrl_on_device selects whether it
+ * is a device or a host pointer.  Both are copied at create time. */
+typedef struct {
+    int d;                      /* 1..3 */
+    int order;                  /* p = degree + 1, 2..9 */
+    int64_t n_knots[3];
+    const double *knots[3];
+    const double *ctrl;
+    int ctrl_on_device;
+} sf_patch_desc;
+
+/* Validate the knot vectors (SF_EKNOT), build the 1D Gauss tables (Sec. 6.1)
+ * on the device and copy the control points.  Enqueues uploads on the
+ * context stream and synchronises once. */
+sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out);
+
+/* Sizes needed to allocate outputs: number of basis functions N, number of
+ * structural nonzeros (exactly prod_k (N_k (2p-1) - p (p-1)), Corollary on
+ * #NZ), number of quadrature points Q.  Any pointer may be NULL. */
+sf_status sf_patch_info(const sf_patch *patch, int64_t *ndof, int64_t *nnz, int64_t *nquad);
+
+/* Coefficient of operator `op` (exactly one of SF_MASS, SF_STIFF): the
+ * reaction coefficient c for the mass form, the scalar diffusion a for the
+ * stiffness form (Example 1 with A = a I).  For SF_COEF_CONST and
+ * SF_COEF_SINPROD `params` is a host pointer to one double; for
+ * SF_COEF_QPVALUES it is a device pointer to Q doubles, which must stay
+ * valid until the next sf_patch_prepare.  Default: constant 1 for both. */
+sf_status sf_patch_set_coef(sf_patch *patch, unsigned op, sf_coef_kind kind, const double *params);
+
+/* Physical coordinates G(x) of all quadrature points, device [Q][d],
+ * lexicographic with quadrature direction 1 fastest (for SF_COEF_QPVALUES
+ * users).  Asynchronous. */
+sf_status sf_patch_quad_points(sf_patch *patch, double *dev_xyz);
+
+/* Geometry step (Sec. 6.3): evaluates G and its Jacobian at all quadrature
+ * points by sum factorization (Algorithm 3), and folds weight, coefficient,
+ * |det J| and J^-1 J^-T into the quadrature-coefficient tensor of each
+ * operator in `ops`, stored at `prec`.  Synchronises once and returns
+ * SF_EGEOM if det J <= 0 anywhere.  Must precede assemble/apply of an
+ * operator at a precision; repeating it is allowed (recomputes). */
+sf_status sf_patch_prepare(sf_patch *patch, unsigned ops, sf_precision prec);
+
+/* Structural CSR pattern (Sec. 3.2): dev_row_ptr [N+1] int64 and
+ * dev_col_ind [nnz] int32, device.  Requires N < 2^31.  Asynchronous. */
+sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col_ind);
+
+/* Global sum-factorized assembly (Algorithm 1) of the operators in `ops`
+ * into the values of the sf_csr_pattern() layout: dev_val_mass and/or
+ * dev_val_stiff, device [nnz] FP64 (the pointer of an operator not in ops
+ * is ignored).  Needs a prior sf_patch_prepare of those operators at
+ * `prec`.  Overwrites the outputs.  Deterministic: no atomics, fixed
+ * summation order.  Asynchronous. */
+sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
+                      double *dev_val_mass, double *dev_val_stiff);
+
+/* Matrix-free product y = A x (Algorithm 3 forward, pointwise coefficient,
+ * Algorithm 2 backward) for one operator op; dev_x, dev_y device [N] FP64,
+ * y overwritten, x and y must not overlap.  Needs a prior sf_patch_prepare
+ * of op at `prec`.  Accumulates through FP64 atomics, so the last bits may
+ * vary between runs.  Asynchronous. */
+sf_status sf_apply(sf_patch *patch, unsigned op, sf_precision prec, const double *dev_x, double *dev_y);
+
+/* Release the patch and its device workspace (synchronises its stream). */
+void sf_patch_destroy(sf_patch *patch);
+
+/* --------------------------------------------------------------- batch */
+
+/* A set of independent patches (block-diagonal operator; Sec. 4, multipatch
+ * example without interface gluing).  The patches stay owned by the caller
+ * and must outlive the batch; all must belong to `ctx`. */
+sf_status sf_batch_create(sf_ctx *ctx, int npatch, sf_patch *const *patches, sf_batch **out);
+
+/* Host arrays [npatch+1]: first row (= first dof) and first nonzero of every
+ * patch in the concatenated block-diagonal CSR / vectors. */
+sf_status sf_batch_offsets(const sf_batch *batch, int64_t *row_off, int64_t *nnz_off);
+
+/* Pattern and values of all patches into concatenated device arrays
+ * (row_ptr [sum N + 1] int64 with global offsets, col_ind [sum nnz] int32
+ * with global column indices, val_* [sum nnz]); every patch must have been
+ * prepared for `ops` at `prec`.  The whole batch is one HIP graph launch. */
+sf_status sf_batch_assemble(sf_batch *batch, unsigned ops, sf_precision prec, int64_t *dev_row_ptr,
+                            int32_t *dev_col_ind, double *dev_val_mass, double *dev_val_stiff);
+
+/* y = blockdiag(A_b) x over the concatenated vectors, one HIP graph launch. */
+sf_status sf_batch_apply(sf_batch *batch, unsigned op, sf_precision prec, const double *dev_x,
+                         double *dev_y);
+
+void sf_batch_destroy(sf_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFIGA_H */

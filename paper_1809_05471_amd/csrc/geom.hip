@@ -1,0 +1,268 @@
+// Geometry step (Sec. 6.3): G and its Jacobian at every quadrature point by
+// sum factorization (Algorithm 3 applied to the control points, with value
+// and derivative tables), then per point: det J (flag if <= 0), J^-1, the
+// coefficient at the physical point G(x), and the folded quadrature
+// coefficients (Example 1 with A = a I):
+//   mass:      w c |det J|
+//   stiffness: w a |det J| (J^-1 J^-T)_ij, i <= j   (J_ik = dG_i/dxhat_k)
+#include "kernels.h"
+
+namespace sfiga {
+
+template <typename T>
+__device__ __forceinline__ void store_coef(void *base, int64_t idx, double v)
+{
+    static_cast<T *>(base)[idx] = (T)v;
+}
+
+__device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3][3], double w, int64_t qlin,
+                                             int q0, int q1, int q2, const PatchView &pv, const GeomOut &o,
+                                             bool f32)
+{
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    if (!(det > 0.0)) *o.bad_det = 1;
+    const double id = 1.0 / det;
+    double inv[3][3];
+    inv[0][0] = c00 * id;
+    inv[1][0] = c01 * id;
+    inv[2][0] = c02 * id;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    const double wd = w * fabs(det);
+    const int Q0 = pv.dir[0].Q, Q1 = pv.dir[1].Q;
+    if (o.xyz) {
+        o.xyz[qlin * 3 + 0] = G[0];
+        o.xyz[qlin * 3 + 1] = G[1];
+        o.xyz[qlin * 3 + 2] = G[2];
+    }
+    if (o.c_mass) {
+        double v = wd * eval_coef(o.coef_mass, G, 3, qlin);
+        int64_t idx = coef_index(3, 1, 0, q0, q1, q2, Q0, Q1);
+        if (f32) store_coef<float>(o.c_mass, idx, v); else store_coef<double>(o.c_mass, idx, v);
+    }
+    if (o.c_stiff) {
+        double s = wd * eval_coef(o.coef_stiff, G, 3, qlin);
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j) {
+                double v = s * (inv[i][0] * inv[j][0] + inv[i][1] * inv[j][1] + inv[i][2] * inv[j][2]);
+                int64_t idx = coef_index(3, 6, sym_comp<3>(i, j), q0, q1, q2, Q0, Q1);
+                if (f32) store_coef<float>(o.c_stiff, idx, v); else store_coef<double>(o.c_stiff, idx, v);
+            }
+    }
+}
+
+// One workgroup per (E1 x E2 element tile, element layer e3).  Threads own a
+// quadrature column (q1, q2); the three contractions run 3 -> 2 -> 1 through
+// LDS, one quadrature plane g3 at a time.
+template <int P>
+__global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomOut o)
+{
+    using TL = Tile<P>;
+    constexpr int NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY;
+    extern __shared__ double smem[];
+    double *cw = smem;                         // [3][P][NY][NX] control points
+    double *sa = cw + 3 * P * NY * NX;         // [6][NY][NX]   B3 c, D3 c at g3
+    double *sb = sa + 6 * NY * NX;             // [9][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
+
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const int e1b = blockIdx.x * TL::E1, e2b = blockIdx.y * TL::E2, e3 = blockIdx.z;
+    const int tid = threadIdx.x;
+    const bool f32 = o.prec == Prec::F32;
+
+    for (int idx = tid; idx < 3 * P * NY * NX; idx += TL::NT) {
+        int lx = idx % NX, r = idx / NX;
+        int ly = r % NY; r /= NY;
+        int s3 = r % P, c = r / P;
+        int n0 = e1b + lx, n1 = e2b + ly, n2 = e3 + s3;
+        double v = 0.0;
+        if (n0 < d0.N && n1 < d1.N) v = pv.ctrl[((int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2)) * 3 + c];
+        cw[idx] = v;
+    }
+    __syncthreads();
+
+    const int tx = tid % TX, ty = tid / TX;
+    const int le1 = tx / P, g1 = tx % P, le2 = ty / P, g2 = ty % P;
+    const int e1 = e1b + le1, e2 = e2b + le2;
+    const bool active = e1 < d0.K && e2 < d1.K;
+
+    for (int g3 = 0; g3 < P; ++g3) {
+        const double *b3 = d2.B + ((int64_t)e3 * P + g3) * P;
+        const double *db3 = d2.D + ((int64_t)e3 * P + g3) * P;
+        for (int idx = tid; idx < NY * NX; idx += TL::NT) {
+            for (int c = 0; c < 3; ++c) {
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    double v = cw[(c * P + s) * NY * NX + idx];
+                    a += b3[s] * v;
+                    b += db3[s] * v;
+                }
+                sa[c * NY * NX + idx] = a;
+                sa[(3 + c) * NY * NX + idx] = b;
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < TY * NX; idx += TL::NT) {
+            int lx = idx % NX, yy = idx / NX;
+            int l2 = yy / P, h2 = yy % P, ee2 = e2b + l2;
+            if (ee2 >= d1.K) continue;
+            const double *b2 = d1.B + ((int64_t)ee2 * P + h2) * P;
+            const double *db2 = d1.D + ((int64_t)ee2 * P + h2) * P;
+            for (int c = 0; c < 3; ++c) {
+                double vb = 0.0, vd = 0.0, wb = 0.0;
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    double a = sa[(c * NY + l2 + s) * NX + lx];
+                    double b = sa[((3 + c) * NY + l2 + s) * NX + lx];
+                    vb += b2[s] * a;
+                    vd += db2[s] * a;
+                    wb += b2[s] * b;
+                }
+                sb[((3 * c + 0) * TY + yy) * NX + lx] = vb;
+                sb[((3 * c + 1) * TY + yy) * NX + lx] = vd;
+                sb[((3 * c + 2) * TY + yy) * NX + lx] = wb;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const double *b1 = d0.B + ((int64_t)e1 * P + g1) * P;
+            const double *db1 = d0.D + ((int64_t)e1 * P + g1) * P;
+            double G[3], J[3][3];
+            for (int c = 0; c < 3; ++c) {
+                double gv = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    double vb = sb[((3 * c + 0) * TY + ty) * NX + le1 + s];
+                    double vd = sb[((3 * c + 1) * TY + ty) * NX + le1 + s];
+                    double wb = sb[((3 * c + 2) * TY + ty) * NX + le1 + s];
+                    gv += b1[s] * vb;
+                    j0 += db1[s] * vb;
+                    j1 += b1[s] * vd;
+                    j2 += b1[s] * wb;
+                }
+                G[c] = gv;
+                J[c][0] = j0;
+                J[c][1] = j1;
+                J[c][2] = j2;
+            }
+            const int q0 = e1 * P + g1, q1 = e2 * P + g2, q2 = e3 * P + g3;
+            const double w = d0.W[q0] * d1.W[q1] * d2.W[q2];
+            const int64_t qlin = (int64_t)q0 + (int64_t)d0.Q * (q1 + (int64_t)d1.Q * q2);
+            pointwise_3d(G, J, w, qlin, q0, q1, q2, pv, o, f32);
+        }
+        __syncthreads();
+    }
+}
+
+// d = 1, 2: one thread per quadrature point, direct sums over the p^d active
+// control points (these sizes are small; d = 3 uses the tile kernel above).
+template <int DIM, int P>
+__global__ void geom_small_kernel(PatchView pv, GeomOut o)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= pv.Q) return;
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1];
+    int q0 = (int)(q % d0.Q), q1 = (DIM == 2) ? (int)(q / d0.Q) : 0;
+    int e0 = q0 / P, g0 = q0 % P, e1 = q1 / P, g1 = q1 % P;
+    double G[2] = {0, 0}, J[2][2] = {{0, 0}, {0, 0}};
+    const double *b0 = d0.B + ((int64_t)e0 * P + g0) * P, *db0 = d0.D + ((int64_t)e0 * P + g0) * P;
+    if (DIM == 1) {
+        for (int s = 0; s < P; ++s) {
+            double c = pv.ctrl[e0 + s];
+            G[0] += b0[s] * c;
+            J[0][0] += db0[s] * c;
+        }
+    } else {
+        const double *b1 = d1.B + ((int64_t)e1 * P + g1) * P, *db1 = d1.D + ((int64_t)e1 * P + g1) * P;
+        for (int s1 = 0; s1 < P; ++s1) {
+            double t0[2] = {0, 0}, t1[2] = {0, 0};
+            for (int s0 = 0; s0 < P; ++s0) {
+                const double *c = pv.ctrl + ((int64_t)(e0 + s0) + (int64_t)d0.N * (e1 + s1)) * 2;
+                for (int i = 0; i < 2; ++i) {
+                    t0[i] += b0[s0] * c[i];
+                    t1[i] += db0[s0] * c[i];
+                }
+            }
+            for (int i = 0; i < 2; ++i) {
+                G[i] += b1[s1] * t0[i];
+                J[i][0] += b1[s1] * t1[i];
+                J[i][1] += db1[s1] * t0[i];
+            }
+        }
+    }
+    double det, inv[2][2];
+    if (DIM == 1) {
+        det = J[0][0];
+        inv[0][0] = 1.0 / det;
+    } else {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        inv[0][0] = J[1][1] / det;
+        inv[0][1] = -J[0][1] / det;
+        inv[1][0] = -J[1][0] / det;
+        inv[1][1] = J[0][0] / det;
+    }
+    if (!(det > 0.0)) *o.bad_det = 1;
+    double w = d0.W[q0] * (DIM == 2 ? d1.W[q1] : 1.0);
+    double wd = w * fabs(det);
+    const bool f32 = o.prec == Prec::F32;
+    if (o.xyz)
+        for (int i = 0; i < DIM; ++i) o.xyz[q * DIM + i] = G[i];
+    if (o.c_mass) {
+        double v = wd * eval_coef(o.coef_mass, G, DIM, q);
+        int64_t idx = coef_index(DIM, 1, 0, q0, q1, 0, d0.Q, d1.Q);
+        if (f32) store_coef<float>(o.c_mass, idx, v); else store_coef<double>(o.c_mass, idx, v);
+    }
+    if (o.c_stiff) {
+        double s = wd * eval_coef(o.coef_stiff, G, DIM, q);
+        constexpr int NC = DIM * (DIM + 1) / 2;
+        for (int i = 0; i < DIM; ++i)
+            for (int j = i; j < DIM; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < DIM; ++k) v += inv[i][k] * inv[j][k];
+                int64_t idx = coef_index(DIM, NC, sym_comp<DIM>(i, j), q0, q1, 0, d0.Q, d1.Q);
+                if (f32) store_coef<float>(o.c_stiff, idx, s * v); else store_coef<double>(o.c_stiff, idx, s * v);
+            }
+    }
+}
+
+template <int P>
+static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream_t s)
+{
+    if (pv.d == 3) {
+        using TL = Tile<P>;
+        dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
+        size_t lds = sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * TL::NY * TL::NX + 9 * TL::TY * TL::NX);
+        hipLaunchKernelGGL(geom3d_kernel<P>, grid, dim3(TL::NT), lds, s, pv, o);
+    } else {
+        int64_t nb = (pv.Q + 255) / 256;
+        if (pv.d == 2)
+            hipLaunchKernelGGL((geom_small_kernel<2, P>), dim3((unsigned)nb), dim3(256), 0, s, pv, o);
+        else
+            hipLaunchKernelGGL((geom_small_kernel<1, P>), dim3((unsigned)nb), dim3(256), 0, s, pv, o);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(const PatchView &pv, const GeomOut &o, hipStream_t s)
+{
+    switch (pv.P) {
+    case 2: return launch_geom_p<2>(pv, o, s);
+    case 3: return launch_geom_p<3>(pv, o, s);
+    case 4: return launch_geom_p<4>(pv, o, s);
+    case 5: return launch_geom_p<5>(pv, o, s);
+    case 6: return launch_geom_p<6>(pv, o, s);
+    case 7: return launch_geom_p<7>(pv, o, s);
+    case 8: return launch_geom_p<8>(pv, o, s);
+    case 9: return launch_geom_p<9>(pv, o, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sfiga

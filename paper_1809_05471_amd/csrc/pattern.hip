@@ -1,0 +1,81 @@
+// Structural CSR pattern (Sec. 3.2): row m holds every column n whose
+// support shares an element with the support of m.  For open knots with
+// simple interior knots this is the tensor product of the 1D bands
+// [max(0, i-p+1), min(N-1, i+p-1)], so row offsets and column indices have
+// closed forms (prefix sums of the 1D band lengths, see RowIndex).
+#include "kernels.h"
+
+namespace sfiga {
+
+__global__ void row_ptr_kernel(RowIndex ri, int64_t nrows, int64_t *row_ptr, int64_t base)
+{
+    int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m > nrows) return;
+    if (m == nrows) {
+        row_ptr[m] = base + ri.T[0] * (ri.d >= 2 ? ri.T[1] : 1) * (ri.d >= 3 ? ri.T[2] : 1);
+        return;
+    }
+    int m0 = (int)(m % ri.N[0]);
+    int64_t r = m / ri.N[0];
+    int m1 = ri.d >= 2 ? (int)(r % ri.N[1]) : 0;
+    int m2 = ri.d >= 3 ? (int)(r / ri.N[1]) : 0;
+    row_ptr[m] = base + row_start(ri, m0, m1, m2);
+}
+
+// One wavefront per row; lanes walk the row's (2p-1)^d band entries.
+__global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int64_t col_base, int64_t nnz_base)
+{
+    const int lane = threadIdx.x % 64;
+    const int64_t m = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+    if (m >= nrows) return;
+    const int P = ri.P;
+    int m0 = (int)(m % ri.N[0]);
+    int64_t r = m / ri.N[0];
+    int m1 = ri.d >= 2 ? (int)(r % ri.N[1]) : 0;
+    int m2 = ri.d >= 3 ? (int)(r / ri.N[1]) : 0;
+    const int lo0 = band_lo(m0, P), l0 = band_len(m0, P, ri.N[0]);
+    const int lo1 = ri.d >= 2 ? band_lo(m1, P) : 0, l1 = ri.d >= 2 ? band_len(m1, P, ri.N[1]) : 1;
+    const int lo2 = ri.d >= 3 ? band_lo(m2, P) : 0, l2 = ri.d >= 3 ? band_len(m2, P, ri.N[2]) : 1;
+    const int64_t start = row_start(ri, m0, m1, m2);
+    const int len = l0 * l1 * l2;
+    int32_t *out = col_ind + nnz_base + start;
+    for (int t = lane; t < len; t += 64) {
+        int a = t % l0, b = (t / l0) % l1, c = t / (l0 * l1);
+        int64_t n = (int64_t)(lo0 + a) + (int64_t)ri.N[0] * ((lo1 + b) + (int64_t)ri.N[1] * (lo2 + c));
+        out[t] = (int32_t)(col_base + n);
+    }
+}
+
+__global__ void fill_kernel(double *y, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = v;
+}
+
+hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)nb), dim3(256), 0, s, y, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
+                          int64_t col_base, int64_t nnz_base, hipStream_t s)
+{
+    // row_ptr gets the entries of this patch at [row_base, row_base + N], values offset by nnz_base
+    if (row_ptr) {
+        int64_t nb = (pv.N + 1 + 255) / 256;
+        hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)nb), dim3(256), 0, s, pv.ri, pv.N, row_ptr + row_base,
+                           nnz_base);
+    }
+    if (col_ind) {
+        int64_t nb = (pv.N + 3) / 4;
+        hipLaunchKernelGGL(col_ind_kernel, dim3((unsigned)nb), dim3(256), 0, s, pv.ri, pv.N, col_ind, col_base,
+                           nnz_base);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sfiga

@@ -1,0 +1,536 @@
+// C ABI of the sfiga library (include/sfiga.h): handles, validation, device
+// workspace and kernel dispatch.  No C++ exception crosses the ABI.
+#include "sfiga.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "spline.h"
+
+using namespace sfiga;
+
+struct sf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+struct sf_patch {
+    sf_ctx *ctx = nullptr;
+    int d = 0, P = 0;
+    Tables1D t[3];
+    double *dB[3] = {nullptr, nullptr, nullptr}, *dD[3] = {nullptr, nullptr, nullptr};
+    double *dW[3] = {nullptr, nullptr, nullptr}, *dX[3] = {nullptr, nullptr, nullptr};
+    int64_t *dS[3] = {nullptr, nullptr, nullptr};
+    double *dctrl = nullptr;
+    int *dflag = nullptr;
+    Coef coef[2];                 // [0] mass, [1] stiffness
+    void *C[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [op][prec]
+    bool ready[2][2] = {{false, false}, {false, false}};
+    PatchView view{};
+};
+
+struct sf_batch {
+    sf_ctx *ctx = nullptr;
+    std::vector<sf_patch *> patches;
+    std::vector<int64_t> row_off, nnz_off;
+    // cached graphs keyed by the launch arguments
+    struct Cached {
+        int kind;                 // 0 assemble, 1 apply
+        unsigned ops;
+        int prec;
+        const void *p0, *p1, *p2, *p3;
+        hipGraphExec_t exec;
+    };
+    std::vector<Cached> graphs;
+};
+
+namespace {
+
+sf_status fail(sf_ctx *ctx, sf_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+sf_status hip_fail(sf_ctx *ctx, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? SF_ENOMEM : SF_EDEVICE, m);
+}
+
+template <typename T>
+hipError_t upload(T **dst, const T *src, size_t n, hipStream_t s)
+{
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * (n ? n : 1));
+    if (e != hipSuccess) return e;
+    if (n) e = hipMemcpyAsync(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+bool prec_index(sf_precision prec, int &pi)
+{
+    if (prec == SF_FP64) { pi = 0; return true; }
+    if (prec == SF_FP32) { pi = 1; return true; }
+    return false;
+}
+
+int ncomp(int op_idx, int d) { return op_idx == 0 ? 1 : d * (d + 1) / 2; }
+
+void free_patch_memory(sf_patch *p)
+{
+    for (int k = 0; k < 3; ++k) {
+        (void)hipFree(p->dB[k]);
+        (void)hipFree(p->dD[k]);
+        (void)hipFree(p->dW[k]);
+        (void)hipFree(p->dX[k]);
+        (void)hipFree(p->dS[k]);
+    }
+    (void)hipFree(p->dctrl);
+    (void)hipFree(p->dflag);
+    for (auto &a : p->C)
+        for (void *c : a) (void)hipFree(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sf_build_target(void) { return "gfx950"; }
+
+sf_status sf_host_tables_1d(const double *knots, int64_t n_knots, int order, int *nel, double *x, double *w,
+                            double *B, double *D)
+{
+    if (!knots) return SF_EINVAL;
+    if (order < 2 || order > kMaxOrder) return SF_EUNSUPPORTED;
+    Tables1D t;
+    bool unsup = false;
+    std::string why = build_tables_1d(knots, n_knots, order, t, unsup);
+    if (!why.empty()) return unsup ? SF_EUNSUPPORTED : SF_EKNOT;
+    if (nel) *nel = t.nel;
+    if (x) std::memcpy(x, t.x.data(), sizeof(double) * t.x.size());
+    if (w) std::memcpy(w, t.w.data(), sizeof(double) * t.w.size());
+    if (B) std::memcpy(B, t.B.data(), sizeof(double) * t.B.size());
+    if (D) std::memcpy(D, t.D.data(), sizeof(double) * t.D.size());
+    return SF_OK;
+}
+
+sf_status sf_ctx_create(int device, void *hip_stream, sf_ctx **out)
+{
+    if (!out) return SF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return SF_EDEVICE;
+    if (device < 0 || device >= n) return SF_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SF_EDEVICE;
+    sf_ctx *c = new (std::nothrow) sf_ctx;
+    if (!c) return SF_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return SF_OK;
+}
+
+void sf_ctx_destroy(sf_ctx *ctx) { delete ctx; }
+
+const char *sf_last_error(const sf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out)
+{
+    if (!ctx) return SF_EINVAL;
+    if (!desc || !out) return fail(ctx, SF_EINVAL, "null argument");
+    *out = nullptr;
+    ctx->err.clear();
+    if (desc->d < 1 || desc->d > 3) return fail(ctx, SF_EUNSUPPORTED, "dimension must be 1, 2 or 3");
+    if (desc->order < 1) return fail(ctx, SF_EINVAL, "order must be >= 1");
+    if (desc->order < 2 || desc->order > kMaxOrder)
+        return fail(ctx, SF_EUNSUPPORTED, "order must be in 2..9");
+    if (!desc->ctrl) return fail(ctx, SF_EINVAL, "null control points");
+    sf_patch *p = new (std::nothrow) sf_patch;
+    if (!p) return fail(ctx, SF_ENOMEM, "host allocation failed");
+    p->ctx = ctx;
+    p->d = desc->d;
+    p->P = desc->order;
+    for (int k = 0; k < desc->d; ++k) {
+        if (!desc->knots[k]) { delete p; return fail(ctx, SF_EINVAL, "null knot vector"); }
+        bool unsup = false;
+        std::string why = build_tables_1d(desc->knots[k], desc->n_knots[k], p->P, p->t[k], unsup);
+        if (!why.empty()) {
+            delete p;
+            return fail(ctx, unsup ? SF_EUNSUPPORTED : SF_EKNOT, "direction " + std::to_string(k + 1) + ": " + why);
+        }
+    }
+    int64_t N = 1, Q = 1, nnz = 1;
+    for (int k = 0; k < p->d; ++k) {
+        N *= p->t[k].nfun;
+        Q *= (int64_t)p->t[k].nel * p->P;
+        nnz *= (int64_t)p->t[k].nfun * (2 * p->P - 1) - (int64_t)p->P * (p->P - 1);
+    }
+    if (N >= (int64_t(1) << 31)) { delete p; return fail(ctx, SF_EUNSUPPORTED, "N >= 2^31 (int32 column indices)"); }
+
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipSuccess;
+    PatchView &v = p->view;
+    std::memset(&v, 0, sizeof(v));
+    v.d = p->d;
+    v.P = p->P;
+    v.ri.P = p->P;
+    v.ri.d = p->d;
+    std::vector<std::vector<int64_t>> S(3);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        Dir &dr = v.dir[k];
+        if (k < p->d) {
+            const Tables1D &t = p->t[k];
+            e = upload(&p->dB[k], t.B.data(), t.B.size(), s);
+            if (e == hipSuccess) e = upload(&p->dD[k], t.D.data(), t.D.size(), s);
+            if (e == hipSuccess) e = upload(&p->dW[k], t.w.data(), t.w.size(), s);
+            if (e == hipSuccess) e = upload(&p->dX[k], t.x.data(), t.x.size(), s);
+            dr.B = p->dB[k];
+            dr.D = p->dD[k];
+            dr.W = p->dW[k];
+            dr.X = p->dX[k];
+            dr.K = t.nel;
+            dr.N = t.nfun;
+            dr.Q = t.nel * p->P;
+            S[k].resize(t.nfun + 1);
+            S[k][0] = 0;
+            for (int i = 0; i < t.nfun; ++i) {
+                int lo = i - p->P + 1 > 0 ? i - p->P + 1 : 0;
+                int hi = i + p->P - 1 < t.nfun - 1 ? i + p->P - 1 : t.nfun - 1;
+                S[k][i + 1] = S[k][i] + (hi - lo + 1);
+            }
+        } else {
+            dr.K = dr.N = dr.Q = 1;
+            S[k] = {0, 1};
+        }
+        if (e == hipSuccess) e = upload(&p->dS[k], S[k].data(), S[k].size(), s);
+        v.ri.S[k] = p->dS[k];
+        v.ri.T[k] = S[k].back();
+        v.ri.N[k] = dr.N;
+    }
+    if (e == hipSuccess) {
+        if (desc->ctrl_on_device) {
+            e = hipMalloc((void **)&p->dctrl, sizeof(double) * N * p->d);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p->dctrl, desc->ctrl, sizeof(double) * N * p->d, hipMemcpyDeviceToDevice, s);
+        } else {
+            e = upload(&p->dctrl, desc->ctrl, (size_t)(N * p->d), s);
+        }
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&p->dflag, sizeof(int));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_patch_memory(p);
+        delete p;
+        return hip_fail(ctx, e, "sf_patch_create");
+    }
+    v.ctrl = p->dctrl;
+    v.N = N;
+    v.Q = Q;
+    v.nnz = nnz;
+    for (auto &c : p->coef) c = Coef{0, 1.0, nullptr};
+    *out = p;
+    return SF_OK;
+}
+
+sf_status sf_patch_info(const sf_patch *p, int64_t *ndof, int64_t *nnz, int64_t *nquad)
+{
+    if (!p) return SF_EINVAL;
+    if (ndof) *ndof = p->view.N;
+    if (nnz) *nnz = p->view.nnz;
+    if (nquad) *nquad = p->view.Q;
+    return SF_OK;
+}
+
+sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const double *params)
+{
+    if (!p) return SF_EINVAL;
+    sf_ctx *ctx = p->ctx;
+    if (op != SF_MASS && op != SF_STIFF) return fail(ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
+    if (!params) return fail(ctx, SF_EINVAL, "null params");
+    Coef c{};
+    switch (kind) {
+    case SF_COEF_CONST: c = Coef{0, params[0], nullptr}; break;
+    case SF_COEF_SINPROD: c = Coef{1, params[0], nullptr}; break;
+    case SF_COEF_QPVALUES: c = Coef{2, 0.0, params}; break;
+    default: return fail(ctx, SF_EINVAL, "unknown coefficient kind");
+    }
+    int oi = op == SF_MASS ? 0 : 1;
+    p->coef[oi] = c;
+    p->ready[oi][0] = p->ready[oi][1] = false;
+    return SF_OK;
+}
+
+sf_status sf_patch_quad_points(sf_patch *p, double *dev_xyz)
+{
+    if (!p) return SF_EINVAL;
+    if (!dev_xyz) return fail(p->ctx, SF_EINVAL, "null output");
+    GeomOut o{};
+    o.xyz = dev_xyz;
+    o.bad_det = p->dflag;
+    o.prec = Prec::F64;
+    o.coef_mass = o.coef_stiff = Coef{0, 1.0, nullptr};
+    hipError_t e = launch_geometry(p->view, o, p->ctx->stream);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "geometry kernel");
+    return SF_OK;
+}
+
+sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
+{
+    if (!p) return SF_EINVAL;
+    sf_ctx *ctx = p->ctx;
+    ctx->err.clear();
+    if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
+    int pi;
+    if (!prec_index(prec, pi)) {
+        if (prec == SF_BF16_SPLIT || prec == SF_FP16_SPLIT) return fail(ctx, SF_EUNSUPPORTED, "precision not built");
+        return fail(ctx, SF_EINVAL, "bad precision");
+    }
+    hipStream_t s = ctx->stream;
+    const size_t esz = pi == 0 ? sizeof(double) : sizeof(float);
+    GeomOut o{};
+    o.prec = pi == 0 ? Prec::F64 : Prec::F32;
+    o.bad_det = p->dflag;
+    o.coef_mass = p->coef[0];
+    o.coef_stiff = p->coef[1];
+    for (int oi = 0; oi < 2; ++oi) {
+        unsigned bit = oi == 0 ? SF_MASS : SF_STIFF;
+        if (!(ops & bit)) continue;
+        if (p->coef[oi].kind == 2 && !p->coef[oi].qp) return fail(ctx, SF_EINVAL, "missing quadrature values");
+        if (!p->C[oi][pi]) {
+            hipError_t e = hipMalloc(&p->C[oi][pi], esz * (size_t)p->view.Q * ncomp(oi, p->d));
+            if (e != hipSuccess) {
+                p->C[oi][pi] = nullptr;
+                return hip_fail(ctx, e, "coefficient tensor allocation");
+            }
+        }
+        p->ready[oi][pi] = false;
+        if (oi == 0) o.c_mass = p->C[oi][pi]; else o.c_stiff = p->C[oi][pi];
+    }
+    hipError_t e = hipMemsetAsync(p->dflag, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_geometry(p->view, o, s);
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "geometry step");
+    if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
+    for (int oi = 0; oi < 2; ++oi)
+        if (ops & (oi == 0 ? SF_MASS : SF_STIFF)) p->ready[oi][pi] = true;
+    return SF_OK;
+}
+
+sf_status sf_csr_pattern(sf_patch *p, int64_t *row_ptr, int32_t *col_ind)
+{
+    if (!p) return SF_EINVAL;
+    if (!row_ptr || !col_ind) return fail(p->ctx, SF_EINVAL, "null output");
+    hipError_t e = launch_pattern(p->view, row_ptr, col_ind, 0, 0, 0, p->ctx->stream);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "pattern kernels");
+    return SF_OK;
+}
+
+static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &pi)
+{
+    sf_ctx *ctx = p->ctx;
+    if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
+    if (!prec_index(prec, pi)) {
+        if (prec == SF_BF16_SPLIT || prec == SF_FP16_SPLIT) return fail(ctx, SF_EUNSUPPORTED, "precision not built");
+        return fail(ctx, SF_EINVAL, "bad precision");
+    }
+    for (int oi = 0; oi < 2; ++oi)
+        if ((ops & (oi == 0 ? SF_MASS : SF_STIFF)) && !p->ready[oi][pi])
+            return fail(ctx, SF_EINVAL, "operator not prepared at this precision (call sf_patch_prepare)");
+    return SF_OK;
+}
+
+static sf_status assemble_into(sf_patch *p, unsigned ops, int pi, double *vm, double *vs, hipStream_t s)
+{
+    for (int oi = 0; oi < 2; ++oi) {
+        if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
+        double *dst = oi == 0 ? vm : vs;
+        hipError_t e = launch_assemble(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], dst, s);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly kernel");
+    }
+    return SF_OK;
+}
+
+sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, double *vs)
+{
+    if (!p) return SF_EINVAL;
+    p->ctx->err.clear();
+    int pi;
+    sf_status st = check_ready(p, ops, prec, pi);
+    if (st != SF_OK) return st;
+    if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(p->ctx, SF_EINVAL, "null output");
+    if (!assemble_supported(p->d, p->P))
+        return fail(p->ctx, SF_EUNSUPPORTED, "assembly for d = 3 is built for orders 2..6");
+    return assemble_into(p, ops, pi, vm, vs, p->ctx->stream);
+}
+
+sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x, double *y)
+{
+    if (!p) return SF_EINVAL;
+    p->ctx->err.clear();
+    if (op != SF_MASS && op != SF_STIFF) return fail(p->ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
+    int pi;
+    sf_status st = check_ready(p, op, prec, pi);
+    if (st != SF_OK) return st;
+    if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
+    if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
+    int oi = op == SF_MASS ? 0 : 1;
+    hipError_t e = launch_apply(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], x, y, p->ctx->stream);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
+    return SF_OK;
+}
+
+void sf_patch_destroy(sf_patch *p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->ctx->stream);
+    free_patch_memory(p);
+    delete p;
+}
+
+// ------------------------------------------------------------------ batch
+
+sf_status sf_batch_create(sf_ctx *ctx, int npatch, sf_patch *const *patches, sf_batch **out)
+{
+    if (!ctx) return SF_EINVAL;
+    if (!out || !patches || npatch < 1) return fail(ctx, SF_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    sf_batch *b = new (std::nothrow) sf_batch;
+    if (!b) return fail(ctx, SF_ENOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->row_off.push_back(0);
+    b->nnz_off.push_back(0);
+    for (int i = 0; i < npatch; ++i) {
+        sf_patch *p = patches[i];
+        if (!p || p->ctx != ctx) { delete b; return fail(ctx, SF_EINVAL, "patch missing or from another context"); }
+        b->patches.push_back(p);
+        b->row_off.push_back(b->row_off.back() + p->view.N);
+        b->nnz_off.push_back(b->nnz_off.back() + p->view.nnz);
+    }
+    if (b->row_off.back() >= (int64_t(1) << 31)) {
+        delete b;
+        return fail(ctx, SF_EUNSUPPORTED, "total N >= 2^31 (int32 column indices)");
+    }
+    *out = b;
+    return SF_OK;
+}
+
+sf_status sf_batch_offsets(const sf_batch *b, int64_t *row_off, int64_t *nnz_off)
+{
+    if (!b) return SF_EINVAL;
+    size_t n = b->row_off.size();
+    if (row_off) std::memcpy(row_off, b->row_off.data(), n * sizeof(int64_t));
+    if (nnz_off) std::memcpy(nnz_off, b->nnz_off.data(), n * sizeof(int64_t));
+    return SF_OK;
+}
+
+static sf_status run_graph(sf_batch *b, int kind, unsigned ops, int pi, const void *p0, const void *p1,
+                           const void *p2, const void *p3,
+                           sf_status (*record)(sf_batch *, unsigned, int, const void *, const void *, const void *,
+                                               const void *, hipStream_t))
+{
+    sf_ctx *ctx = b->ctx;
+    hipStream_t s = ctx->stream;
+    for (auto &c : b->graphs)
+        if (c.kind == kind && c.ops == ops && c.prec == pi && c.p0 == p0 && c.p1 == p1 && c.p2 == p2 && c.p3 == p3) {
+            hipError_t e = hipGraphLaunch(c.exec, s);
+            return e == hipSuccess ? SF_OK : hip_fail(ctx, e, "graph launch");
+        }
+    // a capture needs a non-default stream
+    if (!s) return record(b, ops, pi, p0, p1, p2, p3, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
+    sf_status st = record(b, ops, pi, p0, p1, p2, p3, s);
+    e = hipStreamEndCapture(s, &graph);
+    if (st != SF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
+    b->graphs.push_back(sf_batch::Cached{kind, ops, pi, p0, p1, p2, p3, exec});
+    e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? SF_OK : hip_fail(ctx, e, "graph launch");
+}
+
+static sf_status record_assemble(sf_batch *b, unsigned ops, int pi, const void *rp, const void *ci, const void *vm,
+                                 const void *vs, hipStream_t s)
+{
+    for (size_t i = 0; i < b->patches.size(); ++i) {
+        sf_patch *p = b->patches[i];
+        const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
+        hipError_t e = launch_pattern(p->view, (int64_t *)rp, (int32_t *)ci, r0, r0, z0, s);
+        if (e != hipSuccess) return hip_fail(b->ctx, e, "pattern kernels");
+        sf_status st = assemble_into(p, ops, pi, vm ? (double *)vm + z0 : nullptr, vs ? (double *)vs + z0 : nullptr, s);
+        if (st != SF_OK) return st;
+    }
+    return SF_OK;
+}
+
+static sf_status record_apply(sf_batch *b, unsigned op, int pi, const void *x, const void *y, const void *,
+                              const void *, hipStream_t s)
+{
+    int oi = op == SF_MASS ? 0 : 1;
+    for (size_t i = 0; i < b->patches.size(); ++i) {
+        sf_patch *p = b->patches[i];
+        const int64_t r0 = b->row_off[i];
+        hipError_t e = launch_apply(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi],
+                                    (const double *)x + r0, (double *)y + r0, s);
+        if (e != hipSuccess) return hip_fail(b->ctx, e, "apply kernel");
+    }
+    return SF_OK;
+}
+
+sf_status sf_batch_assemble(sf_batch *b, unsigned ops, sf_precision prec, int64_t *rp, int32_t *ci, double *vm,
+                            double *vs)
+{
+    if (!b) return SF_EINVAL;
+    b->ctx->err.clear();
+    if (!rp || !ci) return fail(b->ctx, SF_EINVAL, "null pattern output");
+    if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(b->ctx, SF_EINVAL, "null output");
+    int pi = 0;
+    for (sf_patch *p : b->patches) {
+        sf_status st = check_ready(p, ops, prec, pi);
+        if (st != SF_OK) return st;
+        if (!assemble_supported(p->d, p->P))
+            return fail(b->ctx, SF_EUNSUPPORTED, "assembly for d = 3 is built for orders 2..6");
+    }
+    return run_graph(b, 0, ops, pi, rp, ci, (ops & SF_MASS) ? vm : nullptr, (ops & SF_STIFF) ? vs : nullptr,
+                     record_assemble);
+}
+
+sf_status sf_batch_apply(sf_batch *b, unsigned op, sf_precision prec, const double *x, double *y)
+{
+    if (!b) return SF_EINVAL;
+    b->ctx->err.clear();
+    if (op != SF_MASS && op != SF_STIFF) return fail(b->ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
+    if (!x || !y || x == y) return fail(b->ctx, SF_EINVAL, "bad vectors");
+    int pi = 0;
+    for (sf_patch *p : b->patches) {
+        sf_status st = check_ready(p, op, prec, pi);
+        if (st != SF_OK) return st;
+    }
+    return run_graph(b, 1, op, pi, x, y, nullptr, nullptr, record_apply);
+}
+
+void sf_batch_destroy(sf_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->ctx->stream);
+    for (auto &c : b->graphs) (void)hipGraphExecDestroy(c.exec);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP64 bar (the paper: sum factorization gives the standard matrix up to
+machine precision): err_A <= 1e-12 and err_y <= 1e-12, metrics in
+tests/gpu_util.py.  FP32 mode: err <= 2e-5 (the coefficient tensor and the
+contractions round to 2^-24; sums of O(p^2) terms per level, three levels).
+Patterns and row pointers are compared bit-exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1809_05471_amd as sf
+from paper_1809_05471_amd import inputs
+from tests.gpu_util import GpuPatch, ctx, err_A, err_y, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def _full_parity(knots, p, ctrl, coef, ops=(sf.SF_MASS, sf.SF_STIFF), prec=sf.SF_FP64, tol=TOL64, seed=0):
+    P = oracle.Problem(knots, p, ctrl, coef)
+    x = inputs.random_vector(P.N, seed)
+    rp_o, ci_o = P.pattern()
+    with GpuPatch(knots, p, ctrl, coef) as g:
+        g.prepare(prec=prec)
+        rp, ci = g.pattern()
+        assert np.array_equal(rp, rp_o)
+        assert np.array_equal(ci.astype(np.int64), ci_o)
+        out = {}
+        for op in ops:
+            _, _, v_o = P.assemble(op, pattern=(rp_o, ci_o))
+            v = g.assemble(op, prec)
+            assert not np.isnan(v).any()
+            eA = err_A(v, v_o)
+            A = oracle.csr_to_dense(rp_o, ci_o, v_o, P.N) if P.N <= 4000 else None
+            y_o = P.apply(op, x)
+            y = g.apply(op, x, prec)
+            absAx = np.abs(A) @ np.abs(x) if A is not None else None
+            if absAx is None:
+                absAx = np.zeros(P.N)
+                np.add.at(absAx, np.repeat(np.arange(P.N), np.diff(rp_o)), np.abs(v_o) * np.abs(x[ci_o]))
+            ey = err_y(y, y_o, absAx)
+            assert eA <= tol, (op, eA)
+            assert ey <= tol, (op, ey)
+            out[op] = (eA, ey)
+        return out
+
+
+def test_small_2d_identity_16x16_p3():
+    """d = 2, 16 x 16 elements, order 3, identity geometry, a = c = 1."""
+    w = inputs.workload_small_2d()
+    _full_parity(w["knots"], w["p"], w["ctrl"], w["coef"])
+
+
+@pytest.mark.parametrize("K,p", [((9, 19, 21), 2), ((6, 15, 17), 3), ((4, 9, 17), 4), ((2, 6, 17), 5),
+                                 ((1, 5, 17), 6)])
+def test_3d_full_parity_several_tiles(K, p):
+    """Several assembly boxes in directions 2 and 3 (ragged last ones) and
+    apply tiles with ragged edges, perturbed geometry, variable coefficient."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=1)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5))
+
+
+@pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((3, 4, 3), 4), ((2, 3, 2), 6)])
+def test_3d_fp32_mode(K, p):
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=4)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP32, tol=TOL32)
+
+
+@pytest.mark.parametrize("K,p", [((17,), 2), ((5,), 5), ((30,), 9)])
+def test_1d(K, p):
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=2)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.3))
+
+
+@pytest.mark.parametrize("K,p", [((7, 5), 2), ((3, 4), 6), ((2, 3), 9)])
+def test_2d_perturbed(K, p):
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=6)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.7))
+
+
+@pytest.mark.parametrize("K,p", [((2, 3, 2), 7), ((1, 2, 2), 8), ((1, 1, 2), 9)])
+def test_3d_high_order_apply(K, p):
+    """Orders 7-9: the geometry step and the apply (d = 3 assembly is built
+    for orders 2..6 and reports SF_EUNSUPPORTED above)."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=3)
+    P = oracle.Problem(kn, p, ctrl, ("sinprod", 0.5))
+    x = inputs.random_vector(P.N, 1)
+    with GpuPatch(kn, p, ctrl, ("sinprod", 0.5)) as g:
+        g.prepare()
+        for op in (sf.SF_MASS, sf.SF_STIFF):
+            rp, ci, v = P.assemble(op)
+            A = oracle.csr_to_dense(rp, ci, v, P.N)
+            y = g.apply(op, x)
+            assert err_y(y, A @ x, np.abs(A) @ np.abs(x)) <= TOL64
+        with pytest.raises(sf.SfError) as e:
+            g.assemble(sf.SF_STIFF)
+        assert e.value.status == sf.SF_EUNSUPPORTED
+
+
+def test_mass_and_stiffness_share_pattern_and_assembly_is_deterministic():
+    kn, ctrl = inputs.perturbed_geometry((5, 6, 7), 3, seed=8)
+    with GpuPatch(kn, 3, ctrl, ("sinprod", 0.5)) as g:
+        g.prepare()
+        a = g.assemble(sf.SF_STIFF)
+        b = g.assemble(sf.SF_STIFF)
+        assert np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def test_qp_values_coefficient_matches_builtin():
+    """SF_COEF_QPVALUES fed with a(G(x)) evaluated at sf_patch_quad_points
+    reproduces SF_COEF_SINPROD."""
+    import torch
+    kn, ctrl = inputs.perturbed_geometry((4, 5, 3), 3, seed=9)
+    with GpuPatch(kn, 3, ctrl, ("sinprod", 0.5)) as g:
+        g.prepare(sf.SF_STIFF)
+        ref = g.assemble(sf.SF_STIFF)
+        xyz = torch.empty((g.Q, 3), dtype=torch.float64, device="cuda")
+        sf.sf_patch_quad_points(ctx(), g.h, xyz)
+        a = 1.0 + 0.5 * torch.prod(torch.sin(2 * np.pi * xyz), dim=1)
+        a = a.contiguous()
+        sf.sf_patch_set_coef(ctx(), g.h, sf.SF_STIFF, sf.SF_COEF_QPVALUES, qp_values=a)
+        g.prepare(sf.SF_STIFF)
+        v = g.assemble(sf.SF_STIFF)
+        assert err_A(v, ref) <= 1e-14
+        # quadrature points agree with the oracle's geometry map
+        P = oracle.Problem(kn, 3, ctrl)
+        assert abs(P.measure() - 1.0) < 0.1
+
+
+def _sampled_parity(w, ops, prec=sf.SF_FP64, tol=TOL64, nrandom=48, assemble=True, coarse=False):
+    kn, p, ctrl, coef, x = w["knots"], w["p"], w["ctrl"], w["coef"], w["x"]
+    P = oracle.Problem(kn, p, ctrl, coef)
+    rows = sample_rows(P.nfun, np.random.default_rng(5), nrandom, coarse)
+    res = {}
+    with GpuPatch(kn, p, ctrl, coef) as g:
+        g.prepare(prec=prec)
+        if assemble:
+            rp, ci = g.pattern()
+            assert rp[-1] == g.nnz
+        for op in ops:
+            ref = P.rows(op, rows)
+            vmax = max(np.abs(v).max() for _, v in ref)
+            absAx = np.array([np.abs(v) @ np.abs(x[c]) for c, v in ref])
+            if assemble:
+                vals = g.assemble(op, prec)
+                worst = 0.0
+                for r, (c, v) in zip(rows, ref):
+                    cg = ci[rp[r]:rp[r + 1]]
+                    assert np.array_equal(cg.astype(np.int64), c)
+                    worst = max(worst, float(np.abs(vals[rp[r]:rp[r + 1]] - v).max()))
+                assert worst / vmax <= tol, (op, worst / vmax)
+                res[("A", op)] = worst / vmax
+            y = g.apply(op, x, prec)
+            y_o = P.apply_rows(op, x, rows)
+            ey = float(np.abs(y[rows] - y_o).max() / absAx.max())
+            assert ey <= tol, (op, ey)
+            res[("y", op)] = ey
+    return res
+
+
+def test_3d_48cubed_p4_sampled_rows():
+    """Full-size d = 3, 48^3 elements, order 4, perturbed geometry,
+    a = 1 + 0.5 sin sin sin: sampled rows of K (and M) and of y = A x, in the
+    launch configuration the benchmark times."""
+    w = inputs.workload_3d((48, 48, 48), 4)
+    _sampled_parity(w, (sf.SF_STIFF, sf.SF_MASS))
+
+
+def test_3d_48cubed_p4_pattern_and_invariants():
+    """Bit-exact pattern against the oracle's, symmetry and K 1 = 0 on the
+    full matrix."""
+    import scipy.sparse as sp
+    w = inputs.workload_3d((48, 48, 48), 4)
+    P = oracle.Problem(w["knots"], 4, w["ctrl"], w["coef"])
+    rp_o, ci_o = P.pattern()
+    with GpuPatch(w["knots"], 4, w["ctrl"], w["coef"]) as g:
+        g.prepare(sf.SF_STIFF)
+        rp, ci = g.pattern()
+        assert np.array_equal(rp, rp_o)
+        assert np.array_equal(ci.astype(np.int64), ci_o)
+        v = g.assemble(sf.SF_STIFF)
+        A = sp.csr_matrix((v, ci, rp), shape=(g.N, g.N))
+        scale = np.abs(v).max()
+        assert abs(A - A.T).max() <= 1e-13 * scale
+        y = A @ np.ones(g.N)
+        assert np.abs(y).max() <= 1e-12 * scale
+        y1 = g.apply(sf.SF_STIFF, np.ones(g.N))
+        assert np.abs(y1).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8, 9])
+def test_order_sweep_apply_sampled(p):
+    """d = 3, K = 127 - p per direction (N = 126^3 for every order), matrix-free
+    stiffness apply on sampled rows, FP64 and FP32."""
+    w = inputs.workload_order_sweep(p)
+    coarse = p >= 6
+    _sampled_parity(w, (sf.SF_STIFF,), nrandom=4 if coarse else 16, assemble=False, coarse=coarse)
+    if p in (4, 6):
+        _sampled_parity(w, (sf.SF_STIFF,), prec=sf.SF_FP32, tol=TOL32, nrandom=4, assemble=False, coarse=True)
+
+
+def test_batched_patches():
+    """Independent patches of different sizes and orders in one batch (one
+    HIP graph per operation): block-diagonal CSR and y against the oracle
+    patch by patch."""
+    import torch
+    Ks, ps = inputs.batched_draw(6, seed=2, kmin=2, kmax=6, pmin=2, pmax=6)
+    patches, probs, xs = [], [], []
+    for b in range(6):
+        kn, ctrl, x = inputs.batched_patch(b, Ks[b], ps[b])
+        g = GpuPatch(kn, int(ps[b]), ctrl)
+        g.prepare()
+        patches.append(g)
+        probs.append(oracle.Problem(kn, int(ps[b]), ctrl))
+        xs.append(x)
+    try:
+        bt = sf.sf_batch_create(ctx(), [g.h for g in patches])
+        ro, zo = sf.sf_batch_offsets(ctx(), bt, 6)
+        Ntot, Z = int(ro[-1]), int(zo[-1])
+        rp = torch.empty(Ntot + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(Z, dtype=torch.int32, device="cuda")
+        vm = torch.empty(Z, dtype=torch.float64, device="cuda")
+        vs = torch.empty(Z, dtype=torch.float64, device="cuda")
+        for rep in range(3):             # the cached graph is replayed; every replay must match
+            vm.fill_(float("nan"))
+            vs.fill_(float("nan"))
+            sf.sf_batch_assemble(ctx(), bt, sf.SF_MASS | sf.SF_STIFF, sf.SF_FP64, rp, ci, vm, vs)
+            torch.cuda.synchronize()
+            rpn, cin, vmn, vsn = rp.cpu().numpy(), ci.cpu().numpy(), vm.cpu().numpy(), vs.cpu().numpy()
+            xall = torch.as_tensor(np.concatenate(xs)).cuda()
+            y = torch.full((Ntot,), float("nan"), dtype=torch.float64, device="cuda")
+            sf.sf_batch_apply(ctx(), bt, sf.SF_STIFF, sf.SF_FP64, xall, y)
+            torch.cuda.synchronize()
+            yn = y.cpu().numpy()
+            for b, P in enumerate(probs):
+                r0, r1, z0 = ro[b], ro[b + 1], zo[b]
+                rp_o, ci_o = P.pattern()
+                assert np.array_equal(rpn[r0:r1 + 1] - z0, rp_o)
+                assert np.array_equal(cin[z0:zo[b + 1]].astype(np.int64) - r0, ci_o)
+                for op, vals in ((sf.SF_MASS, vmn), (sf.SF_STIFF, vsn)):
+                    _, _, v_o = P.assemble(op, pattern=(rp_o, ci_o))
+                    assert err_A(vals[z0:zo[b + 1]], v_o) <= TOL64
+                A = oracle.csr_to_dense(rp_o, ci_o, P.assemble(sf.SF_STIFF, pattern=(rp_o, ci_o))[2], P.N)
+                assert err_y(yn[r0:r1], A @ xs[b], np.abs(A) @ np.abs(xs[b])) <= TOL64
+        sf.sf_batch_destroy(bt)
+    finally:
+        for g in patches:
+            g.close()
+
+
+def test_error_paths():
+    kn, ctrl = inputs.identity_geometry((3, 3, 3), 3)
+    folded = ctrl.copy()
+    folded[:, 0] = -folded[:, 0]                    # mirrored map: det J < 0 everywhere
+    with GpuPatch(kn, 3, folded) as g:
+        with pytest.raises(sf.SfError) as e:
+            g.prepare()
+        assert e.value.status == sf.SF_EGEOM
+    with GpuPatch(kn, 3, ctrl) as g:
+        with pytest.raises(sf.SfError) as e:
+            g.assemble(sf.SF_STIFF)                 # not prepared
+        assert e.value.status == sf.SF_EINVAL
+        with pytest.raises(sf.SfError) as e:
+            g.prepare(prec=sf.SF_BF16_SPLIT + 7)
+        assert e.value.status == sf.SF_EINVAL
+        g.prepare()
+        assert g.assemble(sf.SF_STIFF).shape == (g.nnz,)     # still usable after errors
+    bad = [k.copy() for k in kn]
+    bad[1][3], bad[1][4] = bad[1][4], bad[1][3]
+    with pytest.raises(sf.SfError) as e:
+        GpuPatch(bad, 3, ctrl)
+    assert e.value.status == sf.SF_EKNOT
