@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--elements", type=int, default=48)
     ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--cpu-sample-elements", type=int, default=32,
+    ap.add_argument("--cpu-sample-elements", type=int, default=48,
                     help="elements per direction of the patch the oracle assembles for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()

@@ -52,10 +52,28 @@ struct AsmShape {
     static constexpr int NT = (cmax(cmax(NP * X2, B2 * WPM * 64), B2 * W * W) + 63) / 64 * 64;
     static constexpr int NSLICE = NCOMP * X2 * X1;                 // coefficient slice per plane
     static constexpr int PF = (NSLICE + NT - 1) / NT;              // slice values per thread
+    static constexpr int LSEG = 16;              // rows m3 per workgroup (streamed)
     static constexpr int REGION0 = cmax(NCOMP * X1 * X2P, NP * B2 * W * W);
-    static constexpr int LDS = REGION0 + X2 * NP * W;
+    static constexpr int REGION1 = X2 * NP * W;
+    // 1D tables of the workgroup's elements (B and D), staged once:
+    // direction 1: the p elements of supp(m1); direction 2: the B2+p-1
+    // elements of the rows' support; direction 3: the LSEG+p-1 elements walked
+    static constexpr int T1 = 2 * P * P * P;
+    static constexpr int T2 = 2 * (B2 + P - 1) * P * P;
+    static constexpr int T3 = 2 * (LSEG + P - 1) * P * P;
     static_assert(NT <= AsmCfg<P>::MAXT, "thread count");
 };
+
+// LDS bytes of one workgroup: the coefficient/A2 region and A1 in the
+// contraction type, the tables in double (8-byte aligned after the CT part)
+template <int P, bool STIFF, typename CT>
+constexpr size_t asm_lds_bytes()
+{
+    using S = AsmShape<P, STIFF>;
+    size_t a = sizeof(CT) * (size_t)(S::REGION0 + S::REGION1);
+    a = (a + 15) / 16 * 16;
+    return a + sizeof(double) * (size_t)(S::T1 + S::T2 + S::T3);
+}
 
 // symmetric component of pair (i, j) in the order 00 11 22 01 02 12
 __device__ __forceinline__ int comp3(int i, int j)
@@ -67,7 +85,7 @@ __device__ __forceinline__ int comp3(int i, int j)
 
 template <int P, bool STIFF, typename CT>
 __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchView pv, const CT *__restrict__ C,
-                                                                       double *__restrict__ vals, int L)
+                                                                       double *__restrict__ vals)
 {
     using S = AsmShape<P, STIFF>;
     constexpr int W = S::W, NP = S::NP, NI = S::NI, NCOMP = S::NCOMP, X1 = S::X1;
@@ -76,6 +94,11 @@ __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchVi
     CT *cs = reinterpret_cast<CT *>(smem_raw);   // [NCOMP][X1][X2P]  (aliased by A2 [B2][W][NP][W])
     CT *a2s = cs;
     CT *a1s = cs + S::REGION0;                   // [X2][NP][W]
+    constexpr int L = S::LSEG;
+    double *tab = reinterpret_cast<double *>(smem_raw + (sizeof(CT) * (S::REGION0 + S::REGION1) + 15) / 16 * 16);
+    double *t1B = tab, *t1D = t1B + P * P * P;                          // [le1][g][j]
+    double *t2B = t1D + P * P * P, *t2D = t2B + (B2 + P - 1) * P * P;  // [le2][g][j]
+    double *t3B = t2D + (B2 + P - 1) * P * P, *t3D = t3B + (L + P - 1) * P * P;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
     const int tid = threadIdx.x;
@@ -142,6 +165,29 @@ __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchVi
     const int l2_pair = l2_t / W, l2_c1 = l2_t % W;
     const int l2_i = STIFF ? l2_pair / 3 : 0, l2_j = STIFF ? l2_pair % 3 : 0;
 
+    // stage the 1D tables of this workgroup's elements (zeros outside the mesh)
+    {
+        constexpr int PP = P * P;
+        const int e1b = m1 - P + 1, e2b = a2 - P + 1;
+        for (int i = tid; i < P * PP; i += NT) {
+            const int le = i / PP, e = e1b + le;
+            const bool ok = e >= 0 && e < d0.K;
+            t1B[i] = ok ? d0.B[(int64_t)e * PP + i % PP] : 0.0;
+            t1D[i] = ok ? d0.D[(int64_t)e * PP + i % PP] : 0.0;
+        }
+        for (int i = tid; i < (B2 + P - 1) * PP; i += NT) {
+            const int le = i / PP, e = e2b + le;
+            const bool ok = e >= 0 && e < d1.K;
+            t2B[i] = ok ? d1.B[(int64_t)e * PP + i % PP] : 0.0;
+            t2D[i] = ok ? d1.D[(int64_t)e * PP + i % PP] : 0.0;
+        }
+        for (int i = tid; i < (L + P - 1) * PP; i += NT) {
+            const int le = i / PP, e = e3s + le;
+            const bool ok = e <= e3e;
+            t3B[i] = ok ? d2.B[(int64_t)e * PP + i % PP] : 0.0;
+            t3D[i] = ok ? d2.D[(int64_t)e * PP + i % PP] : 0.0;
+        }
+    }
     load_slice(e3s * P);
     store_slice();
     __syncthreads();
@@ -158,10 +204,10 @@ __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchVi
                     const int e1 = m1 - r;
                     if (e1 < 0 || e1 >= d0.K) continue;
                     const int le1 = P - 1 - r;
-#pragma unroll 1
+#pragma unroll 2
                     for (int g1 = 0; g1 < P; ++g1) {
-                        const double *tb = d0.B + ((int64_t)e1 * P + g1) * P;
-                        const double *td = d0.D + ((int64_t)e1 * P + g1) * P;
+                        const double *tb = t1B + (le1 * P + g1) * P;
+                        const double *td = t1D + (le1 * P + g1) * P;
                         const CT cv = cs[(l1_comp * X1 + le1 * P + g1) * X2P + l1_x2] *
                                       (CT)((STIFF && l1_i == 0) ? td[r] : tb[r]);
 #pragma unroll
@@ -187,10 +233,10 @@ __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchVi
                     const int e2 = l2_m2 - r;
                     if (e2 < 0 || e2 >= d1.K) continue;
                     const int lx2b = (l2_lm2 + P - 1 - r) * P;
-#pragma unroll 1
+#pragma unroll 2
                     for (int g2 = 0; g2 < P; ++g2) {
-                        const double *tb = d1.B + ((int64_t)e2 * P + g2) * P;
-                        const double *td = d1.D + ((int64_t)e2 * P + g2) * P;
+                        const double *tb = t2B + ((l2_lm2 + P - 1 - r) * P + g2) * P;
+                        const double *td = t2D + ((l2_lm2 + P - 1 - r) * P + g2) * P;
                         const CT v = a1s[((lx2b + g2) * NP + l2_pair) * W + l2_c1];
                         const CT tv = (CT)(l2_i == 1 ? td[r] : tb[r]) * v;
 #pragma unroll
@@ -204,8 +250,8 @@ __global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchVi
 
             // ---------------- level 3: fold into the sliding window of rows m3
             if (has_ent) {
-                const double *tb = d2.B + ((int64_t)e3 * P + g3) * P;
-                const double *td = d2.D + ((int64_t)e3 * P + g3) * P;
+                const double *tb = t3B + ((e3 - e3s) * P + g3) * P;
+                const double *td = t3D + ((e3 - e3s) * P + g3) * P;
                 const CT *a2e = a2s + (elm2 * W + ec2) * NP * W + ec1;
                 if constexpr (STIFF) {
                     const double gBB = (double)a2e[0 * W] + (double)a2e[1 * W] + (double)a2e[3 * W] + (double)a2e[4 * W];
@@ -352,8 +398,8 @@ template <int P, bool STIFF, typename CT>
 static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, hipStream_t s)
 {
     using S = AsmShape<P, STIFF>;
-    const int L = 16;
-    const size_t lds = sizeof(CT) * (size_t)S::LDS;
+    constexpr int L = S::LSEG;
+    const size_t lds = asm_lds_bytes<P, STIFF, CT>();
     static size_t lds_set = 0;     // per instantiation: raise the dynamic LDS limit once
     if (lds > lds_set) {
         hipError_t e = hipFuncSetAttribute((const void *)asm3d_kernel<P, STIFF, CT>,
@@ -362,7 +408,7 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, h
         lds_set = lds;
     }
     dim3 grid(pv.dir[0].N, (pv.dir[1].N + S::B2 - 1) / S::B2, (pv.dir[2].N + L - 1) / L);
-    hipLaunchKernelGGL((asm3d_kernel<P, STIFF, CT>), grid, dim3(S::NT), lds, s, pv, C, vals, L);
+    hipLaunchKernelGGL((asm3d_kernel<P, STIFF, CT>), grid, dim3(S::NT), lds, s, pv, C, vals);
     return hipGetLastError();
 }
 
