@@ -27,6 +27,8 @@
 // ((B2+p-1)/B2) and levels 1-2 over the x3 halo ((L+p-1)/L).
 #include "kernels.h"
 
+#include <cstdlib>
+
 namespace sfiga {
 
 template <int P> struct AsmCfg;                 // rows per workgroup in direction 2, max threads
@@ -454,6 +456,11 @@ bool assemble_supported(int d, int P)
 
 hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *C, double *vals, hipStream_t s)
 {
+    // FP64, d = 3: the matrix-core formulation is selectable for comparison
+    // (SFIGA_ASSEMBLY_MFMA=1); the vector kernel is the faster one on this chip
+    static const bool use_mfma = getenv("SFIGA_ASSEMBLY_MFMA") && getenv("SFIGA_ASSEMBLY_MFMA")[0] == '1';
+    if (use_mfma && pv.d == 3 && prec == Prec::F64 && pv.P <= 6)
+        return launch_assemble_mfma(pv, op, (const double *)C, vals, s);
     switch (pv.P) {
     case 2: return launch_asm_p<2>(pv, op, prec, C, vals, s);
     case 3: return launch_asm_p<3>(pv, op, prec, C, vals, s);

@@ -58,6 +58,8 @@ hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, const double *x, double *y,
                         hipStream_t s);
 hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c, double *vals, hipStream_t s);
+// FP64 d = 3 assembly on the matrix cores (orders 2..6)
+hipError_t launch_assemble_mfma(const PatchView &pv, int op, const double *c, double *vals, hipStream_t s);
 
 // true if the (d, P, op, prec) combination has an assembly kernel
 bool assemble_supported(int d, int P);
