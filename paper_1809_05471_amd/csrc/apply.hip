@@ -4,208 +4,262 @@
 // backward: the transposed contractions (Algorithm 2, weights already folded
 // into the coefficient), accumulated into y.
 //
-// d = 3 kernel: one workgroup per (E1 x E2 element tile, element layer e3) -
-// a localized box in the sense of Sec. 4 - with one thread per quadrature
-// column (q1, q2).  The x values of the box's functions are staged in LDS,
-// contractions run direction 3 -> 2 -> 1 and back 1 -> 2 -> 3 one
-// quadrature plane g3 at a time, and the box's partial y is added to global
-// memory with FP64 atomics (the accumulation step of eq. (loc-basis-change)).
-// The coefficient tensor is the only stream that scales with Q; every
-// thread issues its 6 p (stiffness) or p (mass) coefficient loads before the
-// first contraction so they overlap with the forward sweep.
+// d = 3 kernel: one workgroup per (E x E element tile in directions 1 and 2,
+// segment of LZ element layers in direction 3) - a localized box in the
+// sense of Sec. 4 - with one thread per quadrature column (q1, q2).  The
+// workgroup walks its layers in order with sliding windows of the p rows of x
+// and of partial y that the current layer touches; every stage handles all
+// p quadrature planes of the layer at once (5 barriers per layer).  The
+// coefficient tensor is the only stream that scales with Q: the next layer's
+// coefficients are loaded into registers while the current layer is
+// computed.  Partial y rows leave the window through FP64 atomics (the
+// accumulation of eq. (loc-basis-change)), because boxes share functions.
 #include "kernels.h"
 
 namespace sfiga {
 
+template <int P>
+struct STile {
+    static constexpr int E = (16 + P - 1) / P;                 // elements per direction
+    static constexpr int TX = E * P, TY = E * P;               // quadrature columns
+    static constexpr int NX = E + P - 1, NY = E + P - 1;       // functions
+    static constexpr int NT = (TX * TY + 63) / 64 * 64;
+};
+
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(Tile<P>::NT) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
-                                                             const double *__restrict__ x, double *__restrict__ y)
+__global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
+                                                              const double *__restrict__ x, double *__restrict__ y,
+                                                              int LZ)
 {
-    using TL = Tile<P>;
-    constexpr int NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
+    using TL = STile<P>;
+    constexpr int E = TL::E, NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
     constexpr int NF = STIFF ? 3 : 1;      // gradient components or value
     constexpr int NC = STIFF ? 6 : 1;      // coefficient components
+    constexpr int PP = P * P, NXY = NX * NY;
+    // stage buffers: sa holds the forward direction-3 results, then the
+    // pointwise results; sb the forward direction-2 results, then the
+    // backward direction-1 results
+    constexpr int SA = (2 * P * NXY > NF * P * TY * TX) ? 2 * P * NXY : NF * P * TY * TX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    CT *xw = reinterpret_cast<CT *>(smem_raw);   // [P][NY][NX] x on the box's functions
-    CT *yw = xw + P * NY * NX;                   // [P][NY][NX] partial y
-    CT *sa = yw + P * NY * NX;                   // [max(2 NY NX, NF TY NX)] dir-3 results / backward dir-1 results
-    constexpr int SA = (2 * NY * NX > NF * TY * NX) ? 2 * NY * NX : NF * TY * NX;
-    CT *sb = sa + SA;                            // [NF][TY][NX] forward dir-2 results
-    CT *sh = sb + NF * TY * NX;                  // [NF][TY][TX] pointwise results
+    CT *xw = reinterpret_cast<CT *>(smem_raw);   // [P slots][NY][NX], slot = n3 mod p
+    CT *yw = xw + P * NXY;                       // [P slots][NY][NX]
+    CT *sa = yw + P * NXY;                       // [2][P][NY][NX] forward dir 3
+    CT *sh = sa;                                 // [NF][P][TY][TX] pointwise (sa is dead by then)
+    CT *sb = sa + SA;                            // [NF][P][TY][NX] forward dir 2
+    CT *sr = sb;                                 // [NF][P][TY][NX] backward dir 1 (sb is dead by then)
+    CT *t1B = sb + NF * P * TY * NX, *t1D = t1B + E * PP;   // tables [elem][g][j]
+    CT *t2B = t1D + E * PP, *t2D = t2B + E * PP;
+    CT *t3B = t2D + E * PP, *t3D = t3B + PP;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
-    const int e1b = blockIdx.x * TL::E1, e2b = blockIdx.y * TL::E2, e3 = blockIdx.z;
+    const int e1b = blockIdx.x * E, e2b = blockIdx.y * E;
+    const int e3a = blockIdx.z * LZ;
+    const int e3z = (e3a + LZ < d2.K ? e3a + LZ : d2.K) - 1;      // last layer
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int le1 = tx / P, g1 = tx % P, le2 = ty / P, g2 = ty % P;
-    const int e1 = e1b + le1, e2 = e2b + le2;
-    const bool active = e1 < d0.K && e2 < d1.K;
+    const bool active = tid < TX * TY && e1b + le1 < d0.K && e2b + le2 < d1.K;
     const int Q0 = d0.Q, Q1 = d1.Q;
+    const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
 
-    // coefficient loads for the whole column, issued first
-    CT creg[P][NC];
-    if (active) {
-        const int q0 = e1 * P + g1, q1 = e2 * P + g2;
+    // coefficients of one layer for this column: for small p all planes are
+    // held in registers and the next layer's are fetched during this one;
+    // for larger p they are read plane by plane in the pointwise stage
+    constexpr bool PRE = P * NC <= 24;
+    constexpr int NCR = PRE ? P : 1;
+    CT cur[NCR][NC], nxt[NCR][NC];
+    const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
+    auto load_plane = [&](int e3, int g3, CT *dst) {
 #pragma unroll
-        for (int g3 = 0; g3 < P; ++g3)
+        for (int c = 0; c < NC; ++c)
+            dst[c] = active ? C[coef_index(3, NC, c, cq0, cq1, e3 * P + g3, Q0, Q1)] : CT(0);
+    };
+    auto load_layer = [&](int e3, CT (*dst)[NC]) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) creg[g3][c] = C[coef_index(3, NC, c, q0, q1, e3 * P + g3, Q0, Q1)];
-    } else {
-#pragma unroll
-        for (int g3 = 0; g3 < P; ++g3)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) creg[g3][c] = CT(0);
+        for (int g3 = 0; g3 < NCR; ++g3) load_plane(e3, g3, dst[g3]);
+    };
+    auto load_xrow = [&](int n3) {
+        for (int idx = tid; idx < NXY; idx += NT) {
+            const int lx = idx % NX, ly = idx / NX;
+            const int n0 = e1b + lx, n1 = e2b + ly;
+            CT v = CT(0);
+            if (n0 < d0.N && n1 < d1.N) v = (CT)x[n0 + N0 * n1 + N01 * n3];
+            xw[(n3 % P) * NXY + idx] = v;
+        }
+    };
+    auto flush_yrow = [&](int n3) {          // add the finished row to y and clear its slot
+        for (int idx = tid; idx < NXY; idx += NT) {
+            const int lx = idx % NX, ly = idx / NX;
+            const int n0 = e1b + lx, n1 = e2b + ly;
+            CT *slot = yw + (n3 % P) * NXY + idx;
+            if (n0 < d0.N && n1 < d1.N) atomicAdd(&y[n0 + N0 * n1 + N01 * n3], (double)*slot);
+            *slot = CT(0);
+        }
+    };
+
+    if (PRE) load_layer(e3a, cur);
+    for (int i = tid; i < E * PP; i += NT) {
+        const int ea = e1b + i / PP, eb = e2b + i / PP;
+        const int64_t sa1 = (int64_t)(ea < d0.K ? ea : 0) * PP + i % PP;   // in-bounds addresses
+        const int64_t sb2 = (int64_t)(eb < d1.K ? eb : 0) * PP + i % PP;
+        t1B[i] = ea < d0.K ? (CT)d0.B[sa1] : CT(0);
+        t1D[i] = ea < d0.K ? (CT)d0.D[sa1] : CT(0);
+        t2B[i] = eb < d1.K ? (CT)d1.B[sb2] : CT(0);
+        t2D[i] = eb < d1.K ? (CT)d1.D[sb2] : CT(0);
     }
+    for (int i = tid; i < P * NXY; i += NT) yw[i] = CT(0);
+    for (int r = 0; r < P - 1; ++r) load_xrow(e3a + r);
 
-    for (int idx = tid; idx < P * NY * NX; idx += NT) {
-        int lx = idx % NX, r = idx / NX;
-        int ly = r % NY, s3 = r / NY;
-        int n0 = e1b + lx, n1 = e2b + ly, n2 = e3 + s3;
-        CT v = CT(0);
-        if (n0 < d0.N && n1 < d1.N) v = (CT)x[(int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2)];
-        xw[idx] = v;
-        yw[idx] = CT(0);
-    }
-    __syncthreads();
-
-    for (int g3 = 0; g3 < P; ++g3) {
-        const double *b3 = d2.B + ((int64_t)e3 * P + g3) * P;
-        const double *db3 = d2.D + ((int64_t)e3 * P + g3) * P;
-        // forward, direction 3: a = B3 x (and b = D3 x)
-        for (int idx = tid; idx < NY * NX; idx += NT) {
+    for (int e3 = e3a; e3 <= e3z; ++e3) {
+        // ---- new x row entering the window, tables of this layer, next coefficients
+        load_xrow(e3 + P - 1);
+        for (int i = tid; i < PP; i += NT) {
+            t3B[i] = (CT)d2.B[(int64_t)e3 * PP + i];
+            t3D[i] = (CT)d2.D[(int64_t)e3 * PP + i];
+        }
+        if (PRE && e3 < e3z) load_layer(e3 + 1, nxt);
+        __syncthreads();
+        // ---- forward, direction 3: a = B3 x, b = D3 x, every plane
+        for (int idx = tid; idx < P * NXY; idx += NT) {
+            const int g3 = idx / NXY, j = idx % NXY;
             CT a = CT(0), b = CT(0);
 #pragma unroll
             for (int s = 0; s < P; ++s) {
-                CT v = xw[s * NY * NX + idx];
-                a += (CT)b3[s] * v;
-                if (STIFF) b += (CT)db3[s] * v;
+                const CT v = xw[((e3 + s) % P) * NXY + j];
+                a += t3B[g3 * P + s] * v;
+                if (STIFF) b += t3D[g3 * P + s] * v;
             }
-            sa[idx] = a;
-            if (STIFF) sa[NY * NX + idx] = b;
+            sa[g3 * NXY + j] = a;
+            if (STIFF) sa[(P + g3) * NXY + j] = b;
         }
         __syncthreads();
-        // forward, direction 2: B2 a (-> d1 and value), D2 a (-> d2), B2 b (-> d3)
-        for (int idx = tid; idx < TY * NX; idx += NT) {
-            int lx = idx % NX, yy = idx / NX;
-            int l2 = yy / P, h2 = yy % P, ee2 = e2b + l2;
+        // ---- forward, direction 2: B2 a (d1 and value), D2 a (d2), B2 b (d3)
+        for (int idx = tid; idx < P * TY * NX; idx += NT) {
+            const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
+            const int l2 = yy / P, h2 = yy % P;
             CT vb = CT(0), vd = CT(0), wb = CT(0);
-            if (ee2 < d1.K) {
-                const double *b2 = d1.B + ((int64_t)ee2 * P + h2) * P;
-                const double *db2 = d1.D + ((int64_t)ee2 * P + h2) * P;
 #pragma unroll
-                for (int s = 0; s < P; ++s) {
-                    CT a = sa[(l2 + s) * NX + lx];
-                    vb += (CT)b2[s] * a;
-                    if (STIFF) {
-                        CT b = sa[(NY + l2 + s) * NX + lx];
-                        vd += (CT)db2[s] * a;
-                        wb += (CT)b2[s] * b;
-                    }
+            for (int s = 0; s < P; ++s) {
+                const CT a = sa[g3 * NXY + (l2 + s) * NX + lx];
+                const CT bv = t2B[(l2 * P + h2) * P + s];
+                vb += bv * a;
+                if (STIFF) {
+                    vd += t2D[(l2 * P + h2) * P + s] * a;
+                    wb += bv * sa[(P + g3) * NXY + (l2 + s) * NX + lx];
                 }
             }
-            sb[yy * NX + lx] = vb;
+            sb[(0 * P + g3) * TY * NX + yy * NX + lx] = vb;
             if (STIFF) {
-                sb[(TY + yy) * NX + lx] = vd;
-                sb[(2 * TY + yy) * NX + lx] = wb;
+                sb[(1 * P + g3) * TY * NX + yy * NX + lx] = vd;
+                sb[(2 * P + g3) * TY * NX + yy * NX + lx] = wb;
             }
         }
         __syncthreads();
-        // forward, direction 1, and the pointwise coefficient
-        {
-            CT h[NF];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) h[f] = CT(0);
-            if (active) {
-                const double *b1 = d0.B + ((int64_t)e1 * P + g1) * P;
-                const double *db1 = d0.D + ((int64_t)e1 * P + g1) * P;
+        // ---- forward, direction 1, and the pointwise coefficient, every plane
+        if (tid < TX * TY) {
+            const CT *b1 = t1B + (le1 * P + g1) * P, *db1 = t1D + (le1 * P + g1) * P;
+#pragma unroll (PRE ? P : 1)
+            for (int g3 = 0; g3 < P; ++g3) {
+                CT cpl[NC];
+                if (!PRE) load_plane(e3, g3, cpl);
+                const CT *cg = PRE ? cur[g3 < NCR ? g3 : 0] : cpl;
+                CT h[NF];
                 if (STIFF) {
                     CT gr0 = CT(0), gr1 = CT(0), gr2 = CT(0);
 #pragma unroll
                     for (int s = 0; s < P; ++s) {
-                        gr0 += (CT)db1[s] * sb[ty * NX + le1 + s];
-                        gr1 += (CT)b1[s] * sb[(TY + ty) * NX + le1 + s];
-                        gr2 += (CT)b1[s] * sb[(2 * TY + ty) * NX + le1 + s];
+                        gr0 += db1[s] * sb[(0 * P + g3) * TY * NX + ty * NX + le1 + s];
+                        gr1 += b1[s] * sb[(1 * P + g3) * TY * NX + ty * NX + le1 + s];
+                        gr2 += b1[s] * sb[(2 * P + g3) * TY * NX + ty * NX + le1 + s];
                     }
-                    const CT *c = creg[g3];
-                    // components 00 11 22 01 02 12
+                    const CT *c = cg;             // components 00 11 22 01 02 12
                     h[0] = c[0] * gr0 + c[3] * gr1 + c[4] * gr2;
-                    h[1] = c[3] * gr0 + c[1] * gr1 + c[5] * gr2;
-                    h[2] = c[4] * gr0 + c[5] * gr1 + c[2] * gr2;
+                    h[NF > 1 ? 1 : 0] = c[3] * gr0 + c[1] * gr1 + c[5] * gr2;
+                    h[NF > 2 ? 2 : 0] = c[4] * gr0 + c[5] * gr1 + c[2] * gr2;
                 } else {
                     CT u = CT(0);
 #pragma unroll
-                    for (int s = 0; s < P; ++s) u += (CT)b1[s] * sb[ty * NX + le1 + s];
-                    h[0] = creg[g3][0] * u;
+                    for (int s = 0; s < P; ++s) u += b1[s] * sb[g3 * TY * NX + ty * NX + le1 + s];
+                    h[0] = cg[0] * u;
                 }
-            }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) sh[(f * TY + ty) * TX + tx] = h[f];
+                for (int f = 0; f < NF; ++f) sh[(f * P + g3) * TY * TX + ty * TX + tx] = active ? h[f] : CT(0);
+            }
         }
         __syncthreads();
-        // backward, direction 1: r1 = D1^T h1, r2 = B1^T h2, r3 = B1^T h3 (mass: B1^T h)
-        for (int idx = tid; idx < TY * NX; idx += NT) {
-            int lx = idx % NX, yy = idx / NX;
+        // ---- backward, direction 1: D1^T h1, B1^T h2, B1^T h3 (mass: B1^T h)
+        for (int idx = tid; idx < P * TY * NX; idx += NT) {
+            const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
             CT r[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) r[f] = CT(0);
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                const int l1 = lx - j, ee1 = e1b + l1;   // element whose local function j is lx
-                if (l1 < 0 || l1 >= TL::E1 || ee1 >= d0.K) continue;
+                const int l1 = lx - j;                    // element whose local function j is lx
+                if (l1 < 0 || l1 >= E) continue;
+#pragma unroll
                 for (int h1 = 0; h1 < P; ++h1) {
-                    const double bv = d0.B[((int64_t)ee1 * P + h1) * P + j];
-                    const int col = l1 * P + h1;
+                    const CT bv = t1B[(l1 * P + h1) * P + j];
+                    const int col = (g3 * TY + yy) * TX + l1 * P + h1;
                     if (STIFF) {
-                        const double dv = d0.D[((int64_t)ee1 * P + h1) * P + j];
-                        r[0] += (CT)dv * sh[(0 * TY + yy) * TX + col];
-                        r[1] += (CT)bv * sh[(1 * TY + yy) * TX + col];
-                        r[2] += (CT)bv * sh[(2 * TY + yy) * TX + col];
+                        r[0] += t1D[(l1 * P + h1) * P + j] * sh[0 * P * TY * TX + col];
+                        r[NF > 1 ? 1 : 0] += bv * sh[1 * P * TY * TX + col];
+                        r[NF > 2 ? 2 : 0] += bv * sh[2 * P * TY * TX + col];
                     } else {
-                        r[0] += (CT)bv * sh[yy * TX + col];
+                        r[0] += bv * sh[col];
                     }
                 }
             }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) sa[(f * TY + yy) * NX + lx] = r[f];
+            for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
         }
         __syncthreads();
-        // backward, direction 2 then direction 3 into the partial y
-        for (int idx = tid; idx < NY * NX; idx += NT) {
-            int lx = idx % NX, ly = idx / NX;
-            CT sB = CT(0), sD = CT(0);
+        // ---- backward, direction 2, then direction 3 into the y window
+        for (int idx = tid; idx < NXY; idx += NT) {
+            const int lx = idx % NX, ly = idx / NX;
+            CT acc[P];
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int l2 = ly - j, ee2 = e2b + l2;
-                if (l2 < 0 || l2 >= TL::E2 || ee2 >= d1.K) continue;
-                for (int h2 = 0; h2 < P; ++h2) {
-                    const double bv = d1.B[((int64_t)ee2 * P + h2) * P + j];
-                    const int row = l2 * P + h2;
-                    if (STIFF) {
-                        const double dv = d1.D[((int64_t)ee2 * P + h2) * P + j];
-                        sB += (CT)bv * sa[(0 * TY + row) * NX + lx] + (CT)dv * sa[(1 * TY + row) * NX + lx];
-                        sD += (CT)bv * sa[(2 * TY + row) * NX + lx];
-                    } else {
-                        sB += (CT)bv * sa[row * NX + lx];
+            for (int s = 0; s < P; ++s) acc[s] = CT(0);
+#pragma unroll 1
+            for (int g3 = 0; g3 < P; ++g3) {
+                CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l2 = ly - j;
+                    if (l2 < 0 || l2 >= E) continue;
+#pragma unroll
+                    for (int h2 = 0; h2 < P; ++h2) {
+                        const CT bv = t2B[(l2 * P + h2) * P + j];
+                        const int row = (g3 * TY + l2 * P + h2) * NX + lx;
+                        if (STIFF) {
+                            sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
+                            sD += bv * sr[2 * P * TY * NX + row];
+                        } else {
+                            sB += bv * sr[row];
+                        }
                     }
+                }
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    acc[s] += t3B[g3 * P + s] * sB;
+                    if (STIFF) acc[s] += t3D[g3 * P + s] * sD;
                 }
             }
 #pragma unroll
-            for (int s = 0; s < P; ++s) {
-                CT v = (CT)b3[s] * sB;
-                if (STIFF) v += (CT)db3[s] * sD;
-                yw[s * NY * NX + idx] += v;
-            }
+            for (int s = 0; s < P; ++s) yw[((e3 + s) % P) * NXY + idx] += acc[s];
         }
         __syncthreads();
+        // ---- row e3 is complete for this box
+        flush_yrow(e3);
+        if (PRE && e3 < e3z) {
+#pragma unroll
+            for (int g3 = 0; g3 < P; ++g3)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) cur[g3 < NCR ? g3 : 0][c] = nxt[g3 < NCR ? g3 : 0][c];
+        }
     }
-
-    for (int idx = tid; idx < P * NY * NX; idx += NT) {
-        int lx = idx % NX, r = idx / NX;
-        int ly = r % NY, s3 = r / NY;
-        int n0 = e1b + lx, n1 = e2b + ly, n2 = e3 + s3;
-        if (n0 < d0.N && n1 < d1.N)
-            atomicAdd(&y[(int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2)], (double)yw[idx]);
-    }
+    __syncthreads();
+    for (int r = 1; r < P; ++r) flush_yrow(e3z + r);
 }
 
 // d = 1, 2: one thread per element, element-local sum factorization,
@@ -281,12 +335,26 @@ template <int P, bool STIFF, typename CT>
 static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double *x, double *y, hipStream_t s)
 {
     if (pv.d == 3) {
-        using TL = Tile<P>;
+        using TL = STile<P>;
         constexpr int NF = STIFF ? 3 : 1;
-        constexpr int SA = (2 * TL::NY * TL::NX > NF * TL::TY * TL::NX) ? 2 * TL::NY * TL::NX : NF * TL::TY * TL::NX;
-        size_t lds = sizeof(CT) * (2 * P * TL::NY * TL::NX + SA + NF * TL::TY * TL::NX + NF * TL::TY * TL::TX);
-        dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
-        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), grid, dim3(TL::NT), lds, s, pv, C, x, y);
+        constexpr int NXY = TL::NX * TL::NY;
+        constexpr int SA = (2 * P * NXY > NF * P * TL::TY * TL::TX) ? 2 * P * NXY : NF * P * TL::TY * TL::TX;
+        const size_t lds = sizeof(CT) * (size_t)(2 * P * NXY + SA + NF * P * TL::TY * TL::NX + 4 * TL::E * P * P +
+                                                 2 * P * P);
+        static size_t lds_set = 0;
+        if (lds > lds_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)apply3d_kernel<P, STIFF, CT>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lds_set = lds;
+        }
+        const int gx = (pv.dir[0].K + TL::E - 1) / TL::E, gy = (pv.dir[1].K + TL::E - 1) / TL::E;
+        // layers per workgroup: long enough to amortise the window start-up,
+        // short enough to give every CU a few workgroups
+        int LZ = (int)((int64_t)gx * gy * pv.dir[2].K / 2048);
+        LZ = LZ < 2 ? 2 : (LZ > 16 ? 16 : LZ);
+        dim3 grid(gx, gy, (pv.dir[2].K + LZ - 1) / LZ);
+        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), grid, dim3(TL::NT), lds, s, pv, C, x, y, LZ);
     } else {
         int64_t nel = (int64_t)pv.dir[0].K * pv.dir[1].K;
         int64_t nb = (nel + 127) / 128;

@@ -70,6 +70,8 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
     double *cw = smem;                         // [3][P][NY][NX] control points
     double *sa = cw + 3 * P * NY * NX;         // [6][NY][NX]   B3 c, D3 c at g3
     double *sb = sa + 6 * NY * NX;             // [9][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
+    double *t1B = sb + 9 * TY * NX, *t1D = t1B + TL::E1 * P * P;      // tile tables [elem][g][j]
+    double *t2B = t1D + TL::E1 * P * P, *t2D = t2B + TL::E2 * P * P;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
     const int e1b = blockIdx.x * TL::E1, e2b = blockIdx.y * TL::E2, e3 = blockIdx.z;
@@ -84,6 +86,21 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
         double v = 0.0;
         if (n0 < d0.N && n1 < d1.N) v = pv.ctrl[((int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2)) * 3 + c];
         cw[idx] = v;
+    }
+    {
+        constexpr int PP = P * P;
+        for (int i = tid; i < TL::E1 * PP; i += TL::NT) {
+            const int e = e1b + i / PP;
+            const int64_t src = (int64_t)(e < d0.K ? e : 0) * PP + i % PP;   // in-bounds address
+            t1B[i] = e < d0.K ? d0.B[src] : 0.0;
+            t1D[i] = e < d0.K ? d0.D[src] : 0.0;
+        }
+        for (int i = tid; i < TL::E2 * PP; i += TL::NT) {
+            const int e = e2b + i / PP;
+            const int64_t src = (int64_t)(e < d1.K ? e : 0) * PP + i % PP;
+            t2B[i] = e < d1.K ? d1.B[src] : 0.0;
+            t2D[i] = e < d1.K ? d1.D[src] : 0.0;
+        }
     }
     __syncthreads();
 
@@ -113,8 +130,8 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
             int lx = idx % NX, yy = idx / NX;
             int l2 = yy / P, h2 = yy % P, ee2 = e2b + l2;
             if (ee2 >= d1.K) continue;
-            const double *b2 = d1.B + ((int64_t)ee2 * P + h2) * P;
-            const double *db2 = d1.D + ((int64_t)ee2 * P + h2) * P;
+            const double *b2 = t2B + (l2 * P + h2) * P;
+            const double *db2 = t2D + (l2 * P + h2) * P;
             for (int c = 0; c < 3; ++c) {
                 double vb = 0.0, vd = 0.0, wb = 0.0;
 #pragma unroll
@@ -132,8 +149,8 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
         }
         __syncthreads();
         if (active) {
-            const double *b1 = d0.B + ((int64_t)e1 * P + g1) * P;
-            const double *db1 = d0.D + ((int64_t)e1 * P + g1) * P;
+            const double *b1 = t1B + (le1 * P + g1) * P;
+            const double *db1 = t1D + (le1 * P + g1) * P;
             double G[3], J[3][3];
             for (int c = 0; c < 3; ++c) {
                 double gv = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
@@ -238,7 +255,8 @@ static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream
     if (pv.d == 3) {
         using TL = Tile<P>;
         dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
-        size_t lds = sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * TL::NY * TL::NX + 9 * TL::TY * TL::NX);
+        size_t lds = sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * TL::NY * TL::NX + 9 * TL::TY * TL::NX +
+                                       2 * (TL::E1 + TL::E2) * P * P);
         hipLaunchKernelGGL(geom3d_kernel<P>, grid, dim3(TL::NT), lds, s, pv, o);
     } else {
         int64_t nb = (pv.Q + 255) / 256;

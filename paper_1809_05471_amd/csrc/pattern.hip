@@ -22,13 +22,16 @@ __global__ void row_ptr_kernel(RowIndex ri, int64_t nrows, int64_t *row_ptr, int
     row_ptr[m] = base + row_start(ri, m0, m1, m2);
 }
 
-// One wavefront per row; lanes walk the row's (2p-1)^d band entries.
+// One wavefront per row; lanes walk the row's (2p-1)^d band entries.  Rows
+// whose band is not clipped in any direction (the bulk) decompose the entry
+// index with the compile-time band width; clipped rows with their own lengths.
+template <int P>
 __global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int64_t col_base, int64_t nnz_base)
 {
+    constexpr int W = 2 * P - 1;
     const int lane = threadIdx.x % 64;
     const int64_t m = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
     if (m >= nrows) return;
-    const int P = ri.P;
     int m0 = (int)(m % ri.N[0]);
     int64_t r = m / ri.N[0];
     int m1 = ri.d >= 2 ? (int)(r % ri.N[1]) : 0;
@@ -39,10 +42,18 @@ __global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int
     const int64_t start = row_start(ri, m0, m1, m2);
     const int len = l0 * l1 * l2;
     int32_t *out = col_ind + nnz_base + start;
+    const int64_t N0 = ri.N[0], N01 = (int64_t)ri.N[0] * ri.N[1];
+    const int64_t first = col_base + lo0 + N0 * lo1 + N01 * lo2;
+    if (ri.d == 3 && l0 == W && l1 == W && l2 == W) {
+        for (int t = lane; t < W * W * W; t += 64) {
+            const int a = t % W, b = (t / W) % W, c = t / (W * W);
+            out[t] = (int32_t)(first + a + N0 * b + N01 * c);
+        }
+        return;
+    }
     for (int t = lane; t < len; t += 64) {
-        int a = t % l0, b = (t / l0) % l1, c = t / (l0 * l1);
-        int64_t n = (int64_t)(lo0 + a) + (int64_t)ri.N[0] * ((lo1 + b) + (int64_t)ri.N[1] * (lo2 + c));
-        out[t] = (int32_t)(col_base + n);
+        const int a = t % l0, b = (t / l0) % l1, c = t / (l0 * l1);
+        out[t] = (int32_t)(first + a + N0 * b + N01 * c);
     }
 }
 
@@ -72,8 +83,17 @@ hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_in
     }
     if (col_ind) {
         int64_t nb = (pv.N + 3) / 4;
-        hipLaunchKernelGGL(col_ind_kernel, dim3((unsigned)nb), dim3(256), 0, s, pv.ri, pv.N, col_ind, col_base,
-                           nnz_base);
+        dim3 g((unsigned)nb), b(256);
+        switch (pv.P) {
+        case 2: hipLaunchKernelGGL(col_ind_kernel<2>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 3: hipLaunchKernelGGL(col_ind_kernel<3>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 4: hipLaunchKernelGGL(col_ind_kernel<4>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 5: hipLaunchKernelGGL(col_ind_kernel<5>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 6: hipLaunchKernelGGL(col_ind_kernel<6>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 7: hipLaunchKernelGGL(col_ind_kernel<7>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        case 8: hipLaunchKernelGGL(col_ind_kernel<8>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        default: hipLaunchKernelGGL(col_ind_kernel<9>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
+        }
     }
     return hipGetLastError();
 }
