@@ -76,7 +76,15 @@ def _lib():
     for f in (lib.orc_pattern, lib.orc_assemble, lib.orc_rows, lib.orc_apply_rows,
               lib.orc_apply, lib.orc_measure):
         f.restype = ctypes.c_int
+    lib.orc_set_defect.argtypes = [ctypes.c_int]
+    lib.orc_set_defect.restype = None
     return lib
+
+
+def set_defect(k: int) -> None:
+    """Plant mistake k in the oracle's arithmetic (0 removes it).  Only the
+    tests that show the pins catch plausible mistakes use this."""
+    _lib().orc_set_defect(int(k))
 
 
 class OracleError(RuntimeError):

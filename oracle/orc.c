@@ -128,6 +128,14 @@ static int prob_init(prob_t *P, int d, const int *p, const int *nel, const int *
     return ORC_OK;
 }
 
+/* Planted mistakes, for the tests that show the pins catch them (0 = none):
+ * 1 pull-back with J^-1 in place of J^-T, 2 weight of the last direction
+ * dropped, 3 |det J| dropped, 4 sign slip in one entry of the inverse,
+ * 5 coefficient taken at the element centre instead of G(xhat). */
+static int orc_defect = 0;
+
+void orc_set_defect(int k) { orc_defect = k; }
+
 static double coefficient(const prob_t *P, const double *x)
 {
     if (P->coef_kind == 0) return P->coef_val;
@@ -151,7 +159,8 @@ static int eval_qp(const prob_t *P, const int *e, const int *g, qp_t *Q)
 {
     const int d = P->d;
     double wq = 1.0;
-    for (int k = 0; k < d; ++k) wq *= P->w[k][e[k] * P->p[k] + g[k]];
+    for (int k = 0; k < d; ++k)
+        if (!(orc_defect == 2 && k == d - 1)) wq *= P->w[k][e[k] * P->p[k] + g[k]];
 
     /* enumerate active functions lexicographically, direction 1 fastest */
     int nloc = 1;
@@ -203,7 +212,7 @@ static int eval_qp(const prob_t *P, const int *e, const int *g, qp_t *Q)
         det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         if (!(det > 0.0)) return ORC_EGEOM;
         inv[0][0] = J[1][1] / det;
-        inv[0][1] = -J[0][1] / det;
+        inv[0][1] = (orc_defect == 4 ? J[0][1] : -J[0][1]) / det;
         inv[1][0] = -J[1][0] / det;
         inv[1][1] = J[0][0] / det;
     } else {
@@ -223,13 +232,20 @@ static int eval_qp(const prob_t *P, const int *e, const int *g, qp_t *Q)
         inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
         inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
     }
-    Q->wdet = wq * fabs(det);
-    Q->coef = coefficient(P, G);
+    Q->wdet = orc_defect == 3 ? wq : wq * fabs(det);
+    if (orc_defect == 5) {
+        /* element centre of a uniform reference mesh, not G(xhat) */
+        double xr[MAXD];
+        for (int k = 0; k < d; ++k) xr[k] = (e[k] + 0.5) / P->nel[k];
+        Q->coef = coefficient(P, xr);
+    } else {
+        Q->coef = coefficient(P, G);
+    }
     /* physical gradient: (J^-T ghat)_i = sum_k inv[k][i] ghat_k */
     for (int l = 0; l < nloc; ++l)
         for (int i = 0; i < d; ++i) {
             double s = 0.0;
-            for (int k = 0; k < d; ++k) s += inv[k][i] * ghat[l][k];
+            for (int k = 0; k < d; ++k) s += (orc_defect == 1 ? inv[i][k] : inv[k][i]) * ghat[l][k];
             Q->grad[l][i] = s;
         }
     return ORC_OK;

@@ -1,0 +1,51 @@
+"""Each plausible mistake planted in the oracle (on the CPU) makes at least
+one pin fail, and the pins pass again once it is removed.
+
+Planted mistakes: 1 pull-back with J^-1 in place of J^-T (the transpose
+question of Example 1), 2 a dropped quadrature weight, 3 a dropped |det J|,
+4 a sign slip in the inverse, 5 the coefficient evaluated away from the
+physical point G(xhat).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+PIN_CASES = [
+    ("patch test 2D", lambda: pins.test_patch_test_2d((4, 5), 2)),
+    ("affine map 2D", lambda: pins.test_affine_map_2d(np.array([[1.0, 0.3], [0.2, 1.1]]))),
+    ("domain area 2D", lambda: pins.test_mass_sum_equals_domain_area_2d((4, 5), 2)),
+    ("dense brute force 2D", lambda: pins.test_dense_bruteforce_algebraic_form(2, (3, 4), 2, ("sinprod", 0.5))),
+    ("dense brute force 3D", lambda: pins.test_dense_bruteforce_algebraic_form(3, (2, 3, 2), 3, ("sinprod", 0.5))),
+    ("identity Kronecker", lambda: pins.test_identity_geometry_is_kronecker(2, (5, 4), 3)),
+]
+
+
+def _failing_pins():
+    failed = []
+    for name, case in PIN_CASES:
+        try:
+            case()
+        except (AssertionError, oracle.OracleError):
+            failed.append(name)
+    return failed
+
+
+@pytest.fixture
+def planted():
+    yield oracle.set_defect
+    oracle.set_defect(0)
+
+
+@pytest.mark.parametrize("defect", [1, 2, 3, 4, 5])
+def test_planted_mistake_is_caught(planted, defect):
+    planted(defect)
+    failed = _failing_pins()
+    planted(0)
+    assert failed, f"planted mistake {defect} passed every pin"
+
+
+def test_pins_pass_without_plant(planted):
+    planted(0)
+    assert _failing_pins() == []
