@@ -1,80 +1,106 @@
 // Global sum-factorized assembly (Sec. 3, Algorithm 1) into the structural
 // CSR layout.
 //
-// The matrix of a (test dir i, trial dir j) pair of eq. (A-sum) is
+// The matrix of a (test derivative i, trial derivative j) pair of eq. (A-sum) is
 //   A_ij[m][n] = sum_{x3} T3(m3,n3,x3) sum_{x2} T2(m2,n2,x2) sum_{x1} T1(m1,n1,x1) C_ij(x)
 // with T_k(m,n,x) = a_k(m,x) b_k(n,x), a_k = D_k if i == k else B_k (test
 // side), b_k = D_k if j == k else B_k (trial side); the weights are folded
 // into C.  Level k of Algorithm 1 is the sum over x_k; its cost is
 // p_k q_k (prod_{l>=k} #X_l) nnz(A^{k-1}) (eq. (sum factorization-nnz)).
 //
-// d = 3 kernel ("owner computes", deterministic, no atomics): a workgroup
-// owns the rows m1 (one), m2 in [a2, a2+B2) and m3 in [a3, a3+L) with all
-// their columns.  It walks the elements e3 that touch those rows in order;
-// for every quadrature plane x3 it
-//   1. stages the coefficient slice C(x1, x2, x3) for the x1 in the support
-//      of m1 and the x2 of the box's support (prefetched into registers
-//      during the previous plane),
-//   2. level 1: A1[x2][(i,j)][n1] for the fixed m1,
-//   3. level 2: A2[m2][n2][(i,j)][n1] for the box's rows m2,
-//   4. level 3: pairs with equal direction-3 tables are summed (4 groups for
-//      the stiffness: BB, BD, DB, DD; Sec. 3.1 splitting) and folded into a
-//      sliding window of the p rows m3 = e3 .. e3+p-1 held in FP64 registers
-//      (one thread per (m2, n2, n1) entry).
-// Row m3 = e3 is complete after element e3 and is written straight into
-// its CSR slots.  Rows below a3 in the first window are discarded, so each
-// value is written exactly once.  Redundant work: level 1 over the x2 halo
-// ((B2+p-1)/B2) and levels 1-2 over the x3 halo ((L+p-1)/L).
+// d = 3 runs as two kernels over chunks of element layers in direction 3:
+//
+//  asm12_kernel (levels 1 and 2): a workgroup owns one quadrature plane x3
+//    and a tile of T1 rows m1.  It walks the elements e2 of direction 2 in
+//    order; per element it stages the coefficient slice (x1 support of the
+//    tile x the p points of e2), forms level 1 for the tile's rows and all
+//    nine (i, j) pairs, and folds it into a sliding window of the p rows m2
+//    that e2 touches.  Pairs that share their direction-3 tables are summed
+//    at this point (Sec. 3.1 splitting: 4 groups BB, BD, DB, DD for the
+//    stiffness), so the level-2 partial of a plane is
+//      A2[g][m2][m1][n2 - m2 + p - 1][n1 - m1 + p - 1],
+//    written to device memory once per row m2.
+//
+//  asm3_kernel (level 3): one thread per level-2 entry (m1, m2, n1, n2)
+//    walks the elements e3 of a segment of rows m3 and keeps the p x p
+//    window w[r][s] of entries (m3, n3) = (e3 + r, e3 + s).  After element
+//    e3 the entries with r = 0 or s = 0 are complete and go straight to
+//    their CSR slots; the window then shifts along the diagonal.  Each
+//    value is written once, in FP64 (no atomics, deterministic).
+//
+// The level-2 partials of a chunk of element layers live in a device
+// workspace; when the whole patch does not fit, chunks of at least p - 1
+// layers run in order and the level-3 kernel adds the partial sums of
+// entries that straddle two chunks (read-modify-write, same stream).
+//
+// Redundant work: none at levels 1 and 3; level 1 is formed once per
+// (plane, m1 tile, e2); level 3 recomputes the p - 1 element layers before
+// each row segment.
 #include "kernels.h"
 
 #include <cstdlib>
 
 namespace sfiga {
 
-template <int P> struct AsmCfg;                 // rows per workgroup in direction 2, max threads
-template <> struct AsmCfg<2> { static constexpr int B2 = 16, MAXT = 1024; };
-template <> struct AsmCfg<3> { static constexpr int B2 = 16, MAXT = 1024; };
-template <> struct AsmCfg<4> { static constexpr int B2 = 8, MAXT = 512; };
-template <> struct AsmCfg<5> { static constexpr int B2 = 4, MAXT = 512; };
-template <> struct AsmCfg<6> { static constexpr int B2 = 4, MAXT = 512; };
+template <int P> struct A12Cfg;                // threads per workgroup, max rows m1 per tile
+// (T1 (2p - 1) columns fill the waves' 16-column blocks, one block per wave;
+// orders 7-9 use one wave per SIMD for the larger accumulator set)
+template <> struct A12Cfg<2> { static constexpr int NT = 512, T1 = 42; };
+template <> struct A12Cfg<3> { static constexpr int NT = 512, T1 = 25; };
+template <> struct A12Cfg<4> { static constexpr int NT = 512, T1 = 18; };
+template <> struct A12Cfg<5> { static constexpr int NT = 512, T1 = 14; };
+template <> struct A12Cfg<6> { static constexpr int NT = 512, T1 = 11; };
+template <> struct A12Cfg<7> { static constexpr int NT = 256, T1 = 4; };
+template <> struct A12Cfg<8> { static constexpr int NT = 256, T1 = 4; };
+template <> struct A12Cfg<9> { static constexpr int NT = 256, T1 = 3; };
 
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// D[(l / 16) + 4v][l % 16] in element v of lane l
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Pairs (i, j), index 3 i + j, summed into one direction-3 group
+// g = 2 [i == 2] + [j == 2] (BB, BD, DB, DD of Sec. 3.1).
+__device__ __forceinline__ int group_pair(int g, int t)
+{
+    constexpr int tab[4][4] = {{0, 1, 3, 4}, {2, 5, 0, 0}, {6, 7, 0, 0}, {8, 0, 0, 0}};
+    return tab[g][t];
+}
+__host__ __device__ constexpr int group_npairs(int g) { return g == 0 ? 4 : (g == 3 ? 1 : 2); }
 
 template <int P, bool STIFF>
-struct AsmShape {
+struct A12Shape {
     static constexpr int W = 2 * P - 1;          // band width per direction
     static constexpr int NP = STIFF ? 9 : 1;     // (i, j) pairs
-    static constexpr int NI = STIFF ? 3 : 1;     // test derivative directions
+    static constexpr int NG = STIFF ? 4 : 1;     // groups sharing the direction-3 tables
     static constexpr int NCOMP = STIFF ? 6 : 1;  // symmetric coefficient components
-    static constexpr int X1 = P * P;             // x1 points in the support of one m1
-    static constexpr int B2 = AsmCfg<P>::B2;     // rows m2 per workgroup
-    static constexpr int X2 = (B2 + P - 1) * P;  // x2 points in the support of the rows
-    static constexpr int X2P = X2 | 1;           // odd LDS stride
-    static constexpr int WPM = (NP * W + 63) / 64;                 // waves per m2 row, level 2
-    static constexpr int NT = (cmax(cmax(NP * X2, B2 * WPM * 64), B2 * W * W) + 63) / 64 * 64;
-    static constexpr int NSLICE = NCOMP * X2 * X1;                 // coefficient slice per plane
-    static constexpr int PF = (NSLICE + NT - 1) / NT;              // slice values per thread
-    static constexpr int LSEG = 16;              // rows m3 per workgroup (streamed)
-    static constexpr int REGION0 = cmax(NCOMP * X1 * X2P, NP * B2 * W * W);
-    static constexpr int REGION1 = X2 * NP * W;
-    // 1D tables of the workgroup's elements (B and D), staged once:
-    // direction 1: the p elements of supp(m1); direction 2: the B2+p-1
-    // elements of the rows' support; direction 3: the LSEG+p-1 elements walked
-    static constexpr int T1 = 2 * P * P * P;
-    static constexpr int T2 = 2 * (B2 + P - 1) * P * P;
-    static constexpr int T3 = 2 * (LSEG + P - 1) * P * P;
-    static_assert(NT <= AsmCfg<P>::MAXT, "thread count");
+    static constexpr int NT = A12Cfg<P>::NT;
+    static constexpr int T1 = A12Cfg<P>::T1;     // rows m1 per tile (max)
+    static constexpr int XE = T1 + P - 1;        // direction-1 elements touching the tile
+    static constexpr int NSLICE = NCOMP * P * P * XE;        // coefficient slice of one element e2
+    static constexpr int NSTAGE = NSLICE + 2 * P * P;        // + its direction-2 tables
+    static constexpr int PF = (NSTAGE + NT - 1) / NT;        // staged values per thread
+    static constexpr int ITEMS = (T1 * W * W + NT - 1) / NT;  // level-2 entries per thread
+    static constexpr int L1SZ = P * NP * T1 * W;             // level-1 results of one element
+    // level 2 on the matrix cores (FP64): slots (m2 mod p, n2 mod p) as rows,
+    // 16 columns (m1, c1) per wave, K = (pair of the group, x2 point)
+    static constexpr int NSLOT = P * P, MB = (NSLOT + 15) / 16;
+    static constexpr int NW = NT / 64;
+    static constexpr int NCB = (T1 * W + 15) / 16;               // column blocks (max)
+    static constexpr int NBW = (NCB + NW - 1) / NW;              // column blocks per wave
 };
 
-// LDS bytes of one workgroup: the coefficient/A2 region and A1 in the
-// contraction type, the tables in double (8-byte aligned after the CT part)
 template <int P, bool STIFF, typename CT>
-constexpr size_t asm_lds_bytes()
+constexpr size_t a12_lds_bytes()
 {
-    using S = AsmShape<P, STIFF>;
-    size_t a = sizeof(CT) * (size_t)(S::REGION0 + S::REGION1);
+    using S = A12Shape<P, STIFF>;
+    size_t a = sizeof(CT) * (size_t)(S::NSLICE + S::L1SZ);
     a = (a + 15) / 16 * 16;
-    return a + sizeof(double) * (size_t)(S::T1 + S::T2 + S::T3);
+    return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * P * P);
 }
 
 // symmetric component of pair (i, j) in the order 00 11 22 01 02 12
@@ -85,231 +111,342 @@ __device__ __forceinline__ int comp3(int i, int j)
     return a == 0 ? (b == 1 ? 3 : 4) : 5;
 }
 
+// Levels 1 and 2 for the planes x3 in [q3base, q3base + gridDim.y).
+// A2 layout: [plane - q3base][g][m2][m1][c2][c1], c = n - m + p - 1.
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__((AsmShape<P, STIFF>::NT)) void asm3d_kernel(PatchView pv, const CT *__restrict__ C,
-                                                                       double *__restrict__ vals)
+__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
+                                                                        CT *__restrict__ A2, int q3base, int T1r)
 {
-    using S = AsmShape<P, STIFF>;
-    constexpr int W = S::W, NP = S::NP, NI = S::NI, NCOMP = S::NCOMP, X1 = S::X1;
-    constexpr int B2 = S::B2, X2 = S::X2, X2P = S::X2P, NT = S::NT, PF = S::PF, WPM = S::WPM;
+    using S = A12Shape<P, STIFF>;
+    constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
+    constexpr int WW = W * W;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    CT *cs = reinterpret_cast<CT *>(smem_raw);   // [NCOMP][X1][X2P]  (aliased by A2 [B2][W][NP][W])
-    CT *a2s = cs;
-    CT *a1s = cs + S::REGION0;                   // [X2][NP][W]
-    constexpr int L = S::LSEG;
-    double *tab = reinterpret_cast<double *>(smem_raw + (sizeof(CT) * (S::REGION0 + S::REGION1) + 15) / 16 * 16);
-    double *t1B = tab, *t1D = t1B + P * P * P;                          // [le1][g][j]
-    double *t2B = t1D + P * P * P, *t2D = t2B + (B2 + P - 1) * P * P;  // [le2][g][j]
-    double *t3B = t2D + (B2 + P - 1) * P * P, *t3D = t3B + (L + P - 1) * P * P;
+    CT *cs = reinterpret_cast<CT *>(smem_raw);          // [NCOMP][g2][g1][XE]
+    CT *l1 = cs + S::NSLICE;                            // [g2][pair][T1][W]
+    double *t1B = reinterpret_cast<double *>(smem_raw + (sizeof(CT) * (S::NSLICE + S::L1SZ) + 15) / 16 * 16);
+    double *t1D = t1B + P * P * XE;                     // [g1][j][XE]
+    double *t2B = t1D + P * P * XE, *t2D = t2B + P * P; // [g2][j] of the current element e2
 
-    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1];
     const int tid = threadIdx.x;
-    const int m1 = blockIdx.x;
-    const int a2 = blockIdx.y * B2;
-    const int a3 = blockIdx.z * L;
-    const int e3s = a3 - P + 1 > 0 ? a3 - P + 1 : 0;
-    const int e3e = (a3 + L - 1 < d2.K - 1) ? a3 + L - 1 : d2.K - 1;
-    const int Q0 = d0.Q, Q1 = d1.Q;
-    const int q0base = (m1 - P + 1) * P;          // first x1 of the support of m1
-    const int q1base = (a2 - P + 1) * P;          // first x2 of the box support
+    const int b1 = blockIdx.x * T1r;                    // first row m1 of the tile
+    const int nrow1 = min(T1r, d0.N - b1);
+    const int eb1 = b1 - P + 1;                         // first direction-1 element touching the tile
+    const int pl = blockIdx.y;
+    const int q3 = q3base + pl;
+    const int Q0 = d0.Q, Q1 = d1.Q, N1 = d0.N, N2 = d1.N, K1 = d0.K, K2 = d1.K;
+    const int64_t rowsz = (int64_t)N1 * WW;             // one row m2 of A2
+    CT *A2p = A2 + (int64_t)pl * NG * N2 * rowsz;
 
-    // ---- coefficient slice of one plane of constant q3, global order (comp, lx2,
-    //      lx1 fastest); this thread moves elements tid + k NT, k < PF
-    const int64_t plane = (int64_t)NCOMP * Q1 * Q0;
-    CT pf[PF];
-    auto load_slice = [&](int q2) {
-        const CT *base = C + (int64_t)q2 * plane;
+    // direction-1 tables of the tile's elements, [g1][j][le1] (zeros outside the mesh)
+    for (int i = tid; i < P * P * XE; i += NT) {
+        const int le1 = i % XE, gj = i / XE;
+        const int e1 = eb1 + le1;
+        const bool ok = e1 >= 0 && e1 < K1;
+        t1B[i] = ok ? d0.B[(int64_t)e1 * P * P + gj] : 0.0;
+        t1D[i] = ok ? d0.D[(int64_t)e1 * P * P + gj] : 0.0;
+    }
+
+    // staged values of one element e2: coefficient slice (global order comp,
+    // g2, x1 with x1 fastest) followed by the element's direction-2 tables
+    double pf[S::PF];          // slice values (exact in double for either CT) and table values
+    auto load_stage = [&](int e2) {
+        const CT *base = C + (int64_t)q3 * NCOMP * Q1 * Q0;
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
+        for (int k = 0; k < S::PF; ++k) {
             const int idx = tid + k * NT;
-            const int lx1 = idx % X1, r = idx / X1;
-            const int lx2 = r % X2, comp = r / X2;
-            const int q0 = q0base + lx1, q1 = q1base + lx2;
-            const bool ok = idx < S::NSLICE && q0 >= 0 && q0 < Q0 && q1 >= 0 && q1 < Q1;
-            const CT v = base[ok ? (comp * Q1 + q1) * Q0 + q0 : 0];   // in-bounds address on every lane
-            pf[k] = ok ? v : CT(0);
+            if (idx < S::NSLICE) {
+                const int lq1 = idx % (XE * P), r = idx / (XE * P);
+                const int g2 = r % P, comp = r / P;
+                const int q0 = eb1 * P + lq1, q1 = e2 * P + g2;
+                const bool ok = q0 >= 0 && q0 < Q0;
+                const CT v = base[ok ? ((int64_t)comp * Q1 + q1) * Q0 + q0 : 0];
+                pf[k] = ok ? (double)v : 0.0;
+            } else if (idx < S::NSTAGE) {
+                const int t = idx - S::NSLICE;
+                const int which = t / (P * P), gj = t % (P * P);
+                pf[k] = (which ? d1.D : d1.B)[(int64_t)e2 * P * P + gj];
+            }
         }
     };
-    auto store_slice = [&]() {
+    auto store_stage = [&]() {
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
+        for (int k = 0; k < S::PF; ++k) {
             const int idx = tid + k * NT;
-            const int lx1 = idx % X1, r = idx / X1;
-            const int lx2 = r % X2, comp = r / X2;
-            if (idx < S::NSLICE) cs[(comp * X1 + lx1) * X2P + lx2] = pf[k];
+            if (idx < S::NSLICE) {
+                const int lq1 = idx % (XE * P), r = idx / (XE * P);
+                const int le1 = lq1 / P, g1 = lq1 % P;
+                cs[(r * P + g1) * XE + le1] = (CT)pf[k];
+            } else if (idx < S::NSTAGE) {
+                t2B[idx - S::NSLICE] = pf[k];      // t2D follows t2B
+            }
         }
     };
 
-    // ---- level-3 entry owned by this thread
-    const int nent = B2 * W * W;
-    const bool has_ent = tid < nent;
-    const int ec1 = tid % W, ec2 = (tid / W) % W, elm2 = tid / (W * W);
-    const int em2 = a2 + elm2;
-    const int en1 = m1 + ec1 - P + 1, en2 = em2 + ec2 - P + 1;
-    const bool ent_ok = has_ent && em2 < d1.N && en1 >= 0 && en1 < d0.N && en2 >= 0 && en2 < d1.N;
-    double win[P][W];
+    constexpr bool MFMA = sizeof(CT) == sizeof(double);
+    // FP64: level-2 accumulators on the matrix cores
+    d4 macc[MFMA ? S::NBW : 1][NG][MFMA ? S::MB : 1];
+#pragma unroll
+    for (int nb = 0; nb < (MFMA ? S::NBW : 1); ++nb)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int rb = 0; rb < (MFMA ? S::MB : 1); ++rb) macc[nb][g][rb] = d4{0.0, 0.0, 0.0, 0.0};
+    // FP32: level-2 entries of this thread, it = c1 + W (c2 + W lm1)
+    CT acc[MFMA ? 1 : S::ITEMS][P][NG];
+#pragma unroll
+    for (int k = 0; k < (MFMA ? 1 : S::ITEMS); ++k)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) acc[k][r][g] = CT(0);
+    const int nitems = nrow1 * WW;
+
+    load_stage(0);
+    store_stage();
+    __syncthreads();
+
+    for (int e2 = 0; e2 < K2; ++e2) {
+        // ---------------- level 1: contract x1 for every row of the tile
+        for (int it = tid; it < NP * P * nrow1; it += NT) {
+            const int lm1 = it % nrow1, rest = it / nrow1;
+            const int g2 = rest % P, pair = rest / P;
+            const int i = STIFF ? pair / 3 : 1, j = STIFF ? pair % 3 : 1;
+            const int comp = STIFF ? comp3(i, j) : 0;
+            const double *ta = i == 0 ? t1D : t1B;
+            const double *tb = j == 0 ? t1D : t1B;
+            const int m1 = b1 + lm1;
+            CT a[W];
+#pragma unroll
+            for (int c = 0; c < W; ++c) a[c] = CT(0);
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const int e1 = m1 - r;
+                if (e1 < 0 || e1 >= K1) continue;
+                const int le1 = lm1 + P - 1 - r;
+#pragma unroll 2
+                for (int g1 = 0; g1 < P; ++g1) {
+                    const CT cv = cs[((comp * P + g2) * P + g1) * XE + le1] * (CT)ta[(g1 * P + r) * XE + le1];
+#pragma unroll
+                    for (int s = 0; s < P; ++s) a[s - r + P - 1] += cv * (CT)tb[(g1 * P + s) * XE + le1];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < W; ++c) l1[((g2 * NP + pair) * T1 + lm1) * W + c] = a[c];
+        }
+        __syncthreads();
+        const bool more = e2 + 1 < K2;
+        if (more) load_stage(e2 + 1);
+
+        // ---------------- level 2: fold x2 into the rows m2 = e2 + r
+        const bool last = e2 == K2 - 1;
+        if constexpr (MFMA) {
+            // slot (ms, ns) holds entry (m2, n2) with m2 = ms, n2 = ns (mod p);
+            // for element e2 (phase ph) it is (r, s) = (ms - ph, ns - ph) mod p
+            const int ph = e2 % P;
+            const int lane = tid & 63, wave = tid >> 6;
+            const int ncols = nrow1 * W;
+#pragma unroll
+            for (int nb = 0; nb < S::NBW; ++nb) {
+                const int cb = wave + nb * S::NW;
+                if (cb * 16 >= ncols) break;
+                const int col = cb * 16 + (lane & 15);
+                const bool colok = col < ncols;
+                const int kq = lane >> 4;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int nk = (STIFF ? group_npairs(g) : 1) * P;
+#pragma unroll 1
+                    for (int ks = 0; ks < (4 * P + 3) / 4; ++ks) {
+                        if (ks * 4 >= nk) break;
+                        const int k = ks * 4 + kq;
+                        const bool kok = k < nk;
+                        const int pair = STIFF ? group_pair(g, kok ? k / P : 0) : 0;
+                        const int g2 = k % P;
+                        const int pi = STIFF ? pair / 3 : 0, pj = STIFF ? pair % 3 : 0;
+                        const double b = (kok && colok) ? (double)l1[(g2 * NP + pair) * (T1 * W) + col] : 0.0;
+                        const double *ta = pi == 1 ? t2D : t2B, *tb = pj == 1 ? t2D : t2B;
+#pragma unroll
+                        for (int rb = 0; rb < S::MB; ++rb) {
+                            const int i = (lane & 15) + 16 * rb;
+                            const int ms = i / P, ns = i % P;
+                            const int r = (ms - ph + P) % P, sj = (ns - ph + P) % P;
+                            const double a = (kok && i < S::NSLOT) ? ta[g2 * P + r] * tb[g2 * P + sj] : 0.0;
+                            macc[nb][g][rb] = mfma16x16x4(a, b, macc[nb][g][rb]);
+                        }
+                    }
+                }
+                // entries whose last element is e2 (r == 0 or s == 0), all after the last element
+                const int lm1 = col / W, c1 = col % W;
+                CT *dst = A2p + (int64_t)(b1 + lm1) * WW + c1;
+#pragma unroll
+                for (int rb = 0; rb < S::MB; ++rb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = (lane >> 4) + 4 * v + 16 * rb;
+                        const int ms = i / P, ns = i % P;
+                        if (i < S::NSLOT && (last || ms == ph || ns == ph)) {
+                            const int m2 = e2 + (ms - ph + P) % P, n2 = e2 + (ns - ph + P) % P;
+                            const int c2 = n2 - m2 + P - 1;
+#pragma unroll
+                            for (int g = 0; g < NG; ++g) {
+                                if (colok) dst[((int64_t)g * N2 + m2) * rowsz + c2 * W] = macc[nb][g][rb][v];
+                                macc[nb][g][rb][v] = 0.0;
+                            }
+                        }
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < (MFMA ? 1 : S::ITEMS); ++k) {
+                const int it = tid + k * NT;
+                if (it >= nitems) continue;
+                const int c1 = it % W, c2 = (it / W) % W, lm1 = it / WW;
+#pragma unroll 1
+                for (int g2 = 0; g2 < P; ++g2) {
+                    CT L[NP];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) L[a] = l1[((g2 * NP + a) * T1 + lm1) * W + c1];
+#pragma unroll
+                    for (int r = 0; r < P; ++r) {
+                        const int s = r + c2 - (P - 1);
+                        if (s < 0 || s >= P) continue;
+                        const CT Br = (CT)t2B[g2 * P + r], Bs = (CT)t2B[g2 * P + s];
+                        if constexpr (STIFF) {
+                            const CT Dr = (CT)t2D[g2 * P + r], Ds = (CT)t2D[g2 * P + s];
+                            acc[k][r][0] += Br * (Bs * L[0] + Ds * L[1]) + Dr * (Bs * L[3] + Ds * L[4]);
+                            acc[k][r][1] += Bs * (Br * L[2] + Dr * L[5]);
+                            acc[k][r][2] += Br * (Bs * L[6] + Ds * L[7]);
+                            acc[k][r][3] += Br * Bs * L[8];
+                        } else {
+                            acc[k][r][0] += Br * Bs * L[0];
+                        }
+                    }
+                }
+                // row m2 = e2 is complete (and every row of the window after the last element)
+                CT *dst = A2p + (int64_t)b1 * WW + it;
+#pragma unroll
+                for (int r = 0; r < P; ++r) {
+                    if (r > 0 && !last) break;
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) dst[((int64_t)g * N2 + e2 + r) * rowsz] = acc[k][r][g];
+                }
+#pragma unroll
+                for (int r = 0; r + 1 < P; ++r)
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) acc[k][r][g] = acc[k][r + 1][g];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) acc[k][P - 1][g] = CT(0);
+            }
+        }
+        __syncthreads();
+        if (more) {
+            store_stage();
+            __syncthreads();
+        }
+    }
+}
+
+// Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
+// segments seg0 + blockIdx.z (length L each).  One thread per level-2
+// entry (m1, n1, m2 = blockIdx.y, n2).
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__restrict__ A2, double *__restrict__ vals,
+                                                   int s0, int s1, int L, int seg0)
+{
+    constexpr int W = 2 * P - 1, WW = W * W, NG = STIFF ? 4 : 1;
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const int N1 = d0.N, N2 = d1.N;
+    const int64_t rowsz = (int64_t)N1 * WW;
+    const int it = blockIdx.x * 256 + threadIdx.x;
+    if (it >= rowsz) return;
+    const int m2 = blockIdx.y;
+    const int c1 = it % W, c2 = (it / W) % W, m1 = it / WW;
+    const int n1 = m1 + c1 - P + 1, n2 = m2 + c2 - P + 1;
+    if (n1 < 0 || n1 >= N1 || n2 < 0 || n2 >= N2) return;
+    const int a3 = (seg0 + blockIdx.z) * L;
+    const int ebeg = max(s0, a3 - P + 1), eend = min(s1 - 1, a3 + L - 1);
+    if (ebeg > eend) return;
+
+    const RowIndex &ri = pv.ri;
+    const int64_t len1 = band_len(m1, P, N1), len2 = band_len(m2, P, N2);
+    const int64_t R12 = ri.S[1][m2] * ri.T[0] + len2 * ri.S[0][m1];
+    const int64_t off12 = (n1 - band_lo(m1, P)) + (int64_t)(n2 - band_lo(m2, P)) * len1;
+    const int64_t len12 = len1 * len2, T21 = ri.T[1] * ri.T[0];
+    const int N3 = d2.N;
+    auto emit = [&](int m3, int n3, double v) {
+        if (m3 < a3 || m3 >= a3 + L || n3 < 0 || n3 >= N3) return;
+        const int64_t pos = ri.S[2][m3] * T21 + (int64_t)band_len(m3, P, N3) * R12 + off12 +
+                            (int64_t)(n3 - band_lo(m3, P)) * len12;
+        if (s0 > 0 && max(m3, n3) - P + 1 < s0) v += vals[pos];   // partial sum of the previous chunk
+        vals[pos] = v;
+    };
+
+    double w[P][P];
 #pragma unroll
     for (int r = 0; r < P; ++r)
 #pragma unroll
-        for (int c = 0; c < W; ++c) win[r][c] = 0.0;
-
-    // ---- level-1 lane: (pair (i, j), lx2)
-    const bool l1_ok = tid < NP * X2;
-    const int l1_pair = tid / X2, l1_x2 = tid % X2;
-    const int l1_i = STIFF ? l1_pair / 3 : 0, l1_j = STIFF ? l1_pair % 3 : 0;
-    const int l1_comp = STIFF ? comp3(l1_i, l1_j) : 0;
-
-    // ---- level-2 lane: wave -> m2, lane -> (pair, n1 offset)
-    const int wv = tid / 64, ln = tid % 64;
-    const int l2_lm2 = wv / WPM, l2_t = (wv % WPM) * 64 + ln;
-    const int l2_m2 = a2 + l2_lm2;
-    const bool l2_ok = l2_lm2 < B2 && l2_t < NP * W && l2_m2 < d1.N;
-    const int l2_pair = l2_t / W, l2_c1 = l2_t % W;
-    const int l2_i = STIFF ? l2_pair / 3 : 0, l2_j = STIFF ? l2_pair % 3 : 0;
-
-    // stage the 1D tables of this workgroup's elements (zeros outside the mesh)
-    {
-        constexpr int PP = P * P;
-        const int e1b = m1 - P + 1, e2b = a2 - P + 1;
-        for (int i = tid; i < P * PP; i += NT) {
-            const int le = i / PP, e = e1b + le;
-            const bool ok = e >= 0 && e < d0.K;
-            t1B[i] = ok ? d0.B[(int64_t)e * PP + i % PP] : 0.0;
-            t1D[i] = ok ? d0.D[(int64_t)e * PP + i % PP] : 0.0;
-        }
-        for (int i = tid; i < (B2 + P - 1) * PP; i += NT) {
-            const int le = i / PP, e = e2b + le;
-            const bool ok = e >= 0 && e < d1.K;
-            t2B[i] = ok ? d1.B[(int64_t)e * PP + i % PP] : 0.0;
-            t2D[i] = ok ? d1.D[(int64_t)e * PP + i % PP] : 0.0;
-        }
-        for (int i = tid; i < (L + P - 1) * PP; i += NT) {
-            const int le = i / PP, e = e3s + le;
-            const bool ok = e <= e3e;
-            t3B[i] = ok ? d2.B[(int64_t)e * PP + i % PP] : 0.0;
-            t3D[i] = ok ? d2.D[(int64_t)e * PP + i % PP] : 0.0;
-        }
-    }
-    load_slice(e3s * P);
-    store_slice();
-    __syncthreads();
-
-    for (int e3 = e3s; e3 <= e3e; ++e3) {
+        for (int s = 0; s < P; ++s) w[r][s] = 0.0;
+    const int64_t gstride = (int64_t)N2 * rowsz;         // next group of the same plane
+    const CT *src = A2 + (int64_t)m2 * rowsz + it + (int64_t)(ebeg - s0) * P * NG * gstride;
+    // level-2 values of the next plane are loaded one plane ahead
+    CT G[NG], Gn[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) Gn[g] = src[g * gstride];
+    for (int e3 = ebeg; e3 <= eend; ++e3) {
+#pragma unroll 1
         for (int g3 = 0; g3 < P; ++g3) {
-            // ---------------- level 1: contract x1 for the fixed test row m1
-            if (l1_ok) {
-                CT acc[W];
 #pragma unroll
-                for (int c = 0; c < W; ++c) acc[c] = CT(0);
+            for (int g = 0; g < NG; ++g) G[g] = Gn[g];
+            src += NG * gstride;
+            if (g3 + 1 < P || e3 < eend) {
+#pragma unroll
+                for (int g = 0; g < NG; ++g) Gn[g] = src[g * gstride];
+            }
+            const double *tB = d2.B + ((int64_t)e3 * P + g3) * P, *tD = d2.D + ((int64_t)e3 * P + g3) * P;
+            if constexpr (STIFF) {
+                double uB[P], uD[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    uB[s] = tB[s] * (double)G[0] + tD[s] * (double)G[1];
+                    uD[s] = tB[s] * (double)G[2] + tD[s] * (double)G[3];
+                }
 #pragma unroll
                 for (int r = 0; r < P; ++r) {
-                    const int e1 = m1 - r;
-                    if (e1 < 0 || e1 >= d0.K) continue;
-                    const int le1 = P - 1 - r;
-#pragma unroll 2
-                    for (int g1 = 0; g1 < P; ++g1) {
-                        const double *tb = t1B + (le1 * P + g1) * P;
-                        const double *td = t1D + (le1 * P + g1) * P;
-                        const CT cv = cs[(l1_comp * X1 + le1 * P + g1) * X2P + l1_x2] *
-                                      (CT)((STIFF && l1_i == 0) ? td[r] : tb[r]);
+                    const double br = tB[r], dr = tD[r];
 #pragma unroll
-                        for (int s = 0; s < P; ++s)
-                            acc[s - r + P - 1] += cv * (CT)((STIFF && l1_j == 0) ? td[s] : tb[s]);
-                    }
+                    for (int s = 0; s < P; ++s) w[r][s] += br * uB[s] + dr * uD[s];
                 }
+            } else {
+                double u[P];
 #pragma unroll
-                for (int c = 0; c < W; ++c) a1s[(l1_x2 * NP + l1_pair) * W + c] = acc[c];
-            }
-            __syncthreads();
-            // next plane's coefficient slice is fetched while levels 2 and 3 run
-            const bool more = (g3 + 1 < P) || (e3 < e3e);
-            if (more) load_slice(g3 + 1 < P ? e3 * P + g3 + 1 : (e3 + 1) * P);
-
-            // ---------------- level 2: contract x2 for the box rows m2
-            if (l2_ok) {
-                CT acc[W];
-#pragma unroll
-                for (int c = 0; c < W; ++c) acc[c] = CT(0);
+                for (int s = 0; s < P; ++s) u[s] = tB[s] * (double)G[0];
 #pragma unroll
                 for (int r = 0; r < P; ++r) {
-                    const int e2 = l2_m2 - r;
-                    if (e2 < 0 || e2 >= d1.K) continue;
-                    const int lx2b = (l2_lm2 + P - 1 - r) * P;
-#pragma unroll 2
-                    for (int g2 = 0; g2 < P; ++g2) {
-                        const double *tb = t2B + ((l2_lm2 + P - 1 - r) * P + g2) * P;
-                        const double *td = t2D + ((l2_lm2 + P - 1 - r) * P + g2) * P;
-                        const CT v = a1s[((lx2b + g2) * NP + l2_pair) * W + l2_c1];
-                        const CT tv = (CT)(l2_i == 1 ? td[r] : tb[r]) * v;
+                    const double br = tB[r];
 #pragma unroll
-                        for (int s = 0; s < P; ++s) acc[s - r + P - 1] += tv * (CT)(l2_j == 1 ? td[s] : tb[s]);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < W; ++c) a2s[((l2_lm2 * W + c) * NP + l2_pair) * W + l2_c1] = acc[c];
-            }
-            __syncthreads();
-
-            // ---------------- level 3: fold into the sliding window of rows m3
-            if (has_ent) {
-                const double *tb = t3B + ((e3 - e3s) * P + g3) * P;
-                const double *td = t3D + ((e3 - e3s) * P + g3) * P;
-                const CT *a2e = a2s + (elm2 * W + ec2) * NP * W + ec1;
-                if constexpr (STIFF) {
-                    const double gBB = (double)a2e[0 * W] + (double)a2e[1 * W] + (double)a2e[3 * W] + (double)a2e[4 * W];
-                    const double gBD = (double)a2e[2 * W] + (double)a2e[5 * W];
-                    const double gDB = (double)a2e[6 * W] + (double)a2e[7 * W];
-                    const double gDD = (double)a2e[8 * W];
-                    double uB[P], uD[P];
-#pragma unroll
-                    for (int s = 0; s < P; ++s) {
-                        uB[s] = tb[s] * gBB + td[s] * gBD;
-                        uD[s] = tb[s] * gDB + td[s] * gDD;
-                    }
-#pragma unroll
-                    for (int r = 0; r < P; ++r)
-#pragma unroll
-                        for (int s = 0; s < P; ++s) win[r][s - r + P - 1] += tb[r] * uB[s] + td[r] * uD[s];
-                } else {
-                    const double gv = (double)a2e[0];
-#pragma unroll
-                    for (int r = 0; r < P; ++r)
-#pragma unroll
-                        for (int s = 0; s < P; ++s) win[r][s - r + P - 1] += tb[r] * tb[s] * gv;
-                }
-            }
-            __syncthreads();
-            if (more) {
-                store_slice();
-                __syncthreads();
-            }
-        }
-        // ---------------- rows complete after element e3: write and slide
-        const bool last = (e3 == d2.K - 1);
-        if (ent_ok) {
-#pragma unroll
-            for (int r = 0; r < P; ++r) {
-                if (r > 0 && !last) break;
-                const int m3 = e3 + r;
-                if (m3 < a3 || m3 >= a3 + L || m3 >= d2.N) continue;
-                const int lo3 = band_lo(m3, P);
-                const int64_t base = row_start(pv.ri, m1, em2, m3) + col_offset(pv.ri, m1, em2, m3, en1, en2, lo3);
-                const int64_t stride3 = (int64_t)band_len(em2, P, d1.N) * band_len(m1, P, d0.N);
-#pragma unroll
-                for (int c = 0; c < W; ++c) {
-                    const int n3 = m3 + c - P + 1;
-                    if (n3 >= 0 && n3 < d2.N) vals[base + (int64_t)(n3 - lo3) * stride3] = win[r][c];
+                    for (int s = 0; s < P; ++s) w[r][s] += br * u[s];
                 }
             }
         }
-        if (!last) {
+        // entries whose last element is e3: (e3, e3 + s) and (e3 + r, e3)
 #pragma unroll
-            for (int r = 0; r + 1 < P; ++r)
+        for (int s = 0; s < P; ++s) emit(e3, e3 + s, w[0][s]);
 #pragma unroll
-                for (int c = 0; c < W; ++c) win[r][c] = win[r + 1][c];
+        for (int r = 1; r < P; ++r) emit(e3 + r, e3, w[r][0]);
+        if (e3 == s1 - 1) {
+            // end of the chunk: the rest is complete (last layer) or partial
 #pragma unroll
-            for (int c = 0; c < W; ++c) win[P - 1][c] = 0.0;
+            for (int r = 1; r < P; ++r)
+#pragma unroll
+                for (int s = 1; s < P; ++s) emit(e3 + r, e3 + s, w[r][s]);
         }
+#pragma unroll
+        for (int r = 0; r + 1 < P; ++r)
+#pragma unroll
+            for (int s = 0; s + 1 < P; ++s) w[r][s] = w[r + 1][s + 1];
+#pragma unroll
+        for (int k = 0; k < P; ++k) w[P - 1][k] = w[k][P - 1] = 0.0;
     }
 }
 
@@ -396,21 +533,66 @@ __global__ void asm_small_kernel(PatchView pv, const CT *__restrict__ C, double 
 
 // ------------------------------------------------------------------ launch
 
-template <int P, bool STIFF, typename CT>
-static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, hipStream_t s)
+static size_t a2_plane_bytes(const PatchView &pv, int op, Prec prec)
 {
-    using S = AsmShape<P, STIFF>;
-    constexpr int L = S::LSEG;
-    const size_t lds = asm_lds_bytes<P, STIFF, CT>();
+    const int W = 2 * pv.P - 1, NG = op == 2 ? 4 : 1;
+    return (size_t)NG * pv.dir[1].N * pv.dir[0].N * W * W * (prec == Prec::F64 ? sizeof(double) : sizeof(float));
+}
+
+// element layers per chunk for a workspace of the given size (0: too small)
+static int a2_chunk(const PatchView &pv, int op, Prec prec, size_t ws_bytes)
+{
+    const size_t per_layer = a2_plane_bytes(pv, op, prec) * pv.P;
+    const int K3 = pv.dir[2].K;
+    const size_t fit = ws_bytes / per_layer;
+    if (fit >= (size_t)K3) return K3;
+    return (int)fit >= (pv.P - 1 > 1 ? pv.P - 1 : 1) ? (int)fit : 0;
+}
+
+size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t cap)
+{
+    if (pv.d != 3) return 0;
+    const size_t per_layer = a2_plane_bytes(pv, op, prec) * pv.P;
+    const int K3 = pv.dir[2].K;
+    const int minl = pv.P - 1 > 1 ? pv.P - 1 : 1;
+    size_t layers = cap / per_layer;
+    if (layers > (size_t)K3) layers = K3;
+    if (layers < (size_t)(minl < K3 ? minl : K3)) layers = minl < K3 ? minl : K3;
+    return layers * per_layer;
+}
+
+template <int P, bool STIFF, typename CT>
+static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, void *ws, size_t ws_bytes,
+                               hipStream_t s)
+{
+    using S = A12Shape<P, STIFF>;
+    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
     static size_t lds_set = 0;     // per instantiation: raise the dynamic LDS limit once
     if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)asm3d_kernel<P, STIFF, CT>,
+        hipError_t e = hipFuncSetAttribute((const void *)asm12_kernel<P, STIFF, CT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    dim3 grid(pv.dir[0].N, (pv.dir[1].N + S::B2 - 1) / S::B2, (pv.dir[2].N + L - 1) / L);
-    hipLaunchKernelGGL((asm3d_kernel<P, STIFF, CT>), grid, dim3(S::NT), lds, s, pv, C, vals);
+    const int op = STIFF ? 2 : 1;
+    const Prec prec = sizeof(CT) == sizeof(double) ? Prec::F64 : Prec::F32;
+    const int chunk = a2_chunk(pv, op, prec, ws_bytes);
+    if (chunk == 0 || !ws) return hipErrorInvalidValue;
+    const int N1 = pv.dir[0].N, N2 = pv.dir[1].N, N3 = pv.dir[2].N, K3 = pv.dir[2].K;
+    const int ntile = (N1 + S::T1 - 1) / S::T1;
+    const int T1r = (N1 + ntile - 1) / ntile;               // balanced tiles of at most T1 rows
+    const int nseg = (N3 + 15) / 16, L = (N3 + nseg - 1) / nseg;
+    const int64_t rowsz = (int64_t)N1 * S::W * S::W;
+    CT *A2 = static_cast<CT *>(ws);
+    for (int s0 = 0; s0 < K3; s0 += chunk) {
+        const int s1 = s0 + chunk < K3 ? s0 + chunk : K3;
+        hipLaunchKernelGGL((asm12_kernel<P, STIFF, CT>), dim3(ntile, (s1 - s0) * P), dim3(S::NT), lds, s, pv, C, A2,
+                           s0 * P, T1r);
+        const int last_row = s1 + P - 2 < N3 - 1 ? s1 + P - 2 : N3 - 1;
+        const int seg0 = s0 / L, seg1 = last_row / L;
+        hipLaunchKernelGGL((asm3_kernel<P, STIFF, CT>), dim3((unsigned)((rowsz + 255) / 256), N2, seg1 - seg0 + 1),
+                           dim3(256), 0, s, pv, (const CT *)A2, vals, s0, s1, L, seg0);
+    }
     return hipGetLastError();
 }
 
@@ -427,49 +609,37 @@ static hipError_t launch_asm_small(const PatchView &pv, const CT *C, double *val
     return hipGetLastError();
 }
 
+template <int P, typename CT>
+static hipError_t launch_asm_pt(const PatchView &pv, int op, const void *C, double *vals, void *ws,
+                                size_t ws_bytes, hipStream_t s)
+{
+    const CT *c = static_cast<const CT *>(C);
+    if (pv.d == 3)
+        return op == 2 ? launch_asm3d<P, true, CT>(pv, c, vals, ws, ws_bytes, s)
+                       : launch_asm3d<P, false, CT>(pv, c, vals, ws, ws_bytes, s);
+    return op == 2 ? launch_asm_small<P, true, CT>(pv, c, vals, s) : launch_asm_small<P, false, CT>(pv, c, vals, s);
+}
+
 template <int P>
-static hipError_t launch_asm_p(const PatchView &pv, int op, Prec prec, const void *C, double *vals, hipStream_t s)
+static hipError_t launch_asm_p(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
+                               size_t ws_bytes, hipStream_t s)
 {
-    if (pv.d == 3) {
-        if constexpr (P <= 6) {
-            if (prec == Prec::F64)
-                return op == 2 ? launch_asm3d<P, true, double>(pv, (const double *)C, vals, s)
-                               : launch_asm3d<P, false, double>(pv, (const double *)C, vals, s);
-            return op == 2 ? launch_asm3d<P, true, float>(pv, (const float *)C, vals, s)
-                           : launch_asm3d<P, false, float>(pv, (const float *)C, vals, s);
-        } else {
-            return hipErrorInvalidValue;
-        }
-    }
-    if (prec == Prec::F64)
-        return op == 2 ? launch_asm_small<P, true, double>(pv, (const double *)C, vals, s)
-                       : launch_asm_small<P, false, double>(pv, (const double *)C, vals, s);
-    return op == 2 ? launch_asm_small<P, true, float>(pv, (const float *)C, vals, s)
-                   : launch_asm_small<P, false, float>(pv, (const float *)C, vals, s);
+    return prec == Prec::F64 ? launch_asm_pt<P, double>(pv, op, C, vals, ws, ws_bytes, s)
+                             : launch_asm_pt<P, float>(pv, op, C, vals, ws, ws_bytes, s);
 }
 
-bool assemble_supported(int d, int P)
+hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
+                           size_t ws_bytes, hipStream_t s)
 {
-    if (P < 2 || P > 9) return false;
-    return d < 3 || P <= 6;
-}
-
-hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *C, double *vals, hipStream_t s)
-{
-    // FP64, d = 3: the matrix-core formulation is selectable for comparison
-    // (SFIGA_ASSEMBLY_MFMA=1); the vector kernel is the faster one on this chip
-    static const bool use_mfma = getenv("SFIGA_ASSEMBLY_MFMA") && getenv("SFIGA_ASSEMBLY_MFMA")[0] == '1';
-    if (use_mfma && pv.d == 3 && prec == Prec::F64 && pv.P <= 6)
-        return launch_assemble_mfma(pv, op, (const double *)C, vals, s);
     switch (pv.P) {
-    case 2: return launch_asm_p<2>(pv, op, prec, C, vals, s);
-    case 3: return launch_asm_p<3>(pv, op, prec, C, vals, s);
-    case 4: return launch_asm_p<4>(pv, op, prec, C, vals, s);
-    case 5: return launch_asm_p<5>(pv, op, prec, C, vals, s);
-    case 6: return launch_asm_p<6>(pv, op, prec, C, vals, s);
-    case 7: return launch_asm_p<7>(pv, op, prec, C, vals, s);
-    case 8: return launch_asm_p<8>(pv, op, prec, C, vals, s);
-    case 9: return launch_asm_p<9>(pv, op, prec, C, vals, s);
+    case 2: return launch_asm_p<2>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 3: return launch_asm_p<3>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 4: return launch_asm_p<4>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 5: return launch_asm_p<5>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 6: return launch_asm_p<6>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 7: return launch_asm_p<7>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 8: return launch_asm_p<8>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 9: return launch_asm_p<9>(pv, op, prec, C, vals, ws, ws_bytes, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -57,11 +57,12 @@ hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
 // op: 1 mass, 2 stiffness; c: coefficient tensor of that op at prec
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, const double *x, double *y,
                         hipStream_t s);
-hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c, double *vals, hipStream_t s);
-// FP64 d = 3 assembly on the matrix cores (orders 2..6)
-hipError_t launch_assemble_mfma(const PatchView &pv, int op, const double *c, double *vals, hipStream_t s);
-
-// true if the (d, P, op, prec) combination has an assembly kernel
-bool assemble_supported(int d, int P);
+// ws: device workspace of ws_bytes for the d = 3 level-2 partials (see
+// assemble_workspace_bytes; unused for d <= 2)
+hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c, double *vals, void *ws,
+                           size_t ws_bytes, hipStream_t s);
+// workspace of the d = 3 assembly of op at prec: whole patch if it fits in
+// cap bytes, else chunks of element layers (never fewer than p - 1)
+size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t cap);
 
 }  // namespace sfiga

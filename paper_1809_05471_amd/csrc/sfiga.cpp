@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -33,6 +34,10 @@ struct sf_patch {
     Coef coef[2];                 // [0] mass, [1] stiffness
     void *C[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [op][prec]
     bool ready[2][2] = {{false, false}, {false, false}};
+    // level-2 workspace of the d = 3 assembly, sized once for the largest
+    // (operator, precision) so that captured graphs never see it move
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
     PatchView view{};
 };
 
@@ -94,6 +99,7 @@ void free_patch_memory(sf_patch *p)
     }
     (void)hipFree(p->dctrl);
     (void)hipFree(p->dflag);
+    (void)hipFree(p->ws);
     for (auto &a : p->C)
         for (void *c : a) (void)hipFree(c);
 }
@@ -348,12 +354,36 @@ static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &
     return SF_OK;
 }
 
+// Upper bound of the assembly workspace (SFIGA_WORKSPACE_MB, default 4096):
+// patches whose level-2 partials exceed it are assembled in chunks of
+// element layers.
+static size_t workspace_cap()
+{
+    const char *v = getenv("SFIGA_WORKSPACE_MB");
+    long mb = v ? atol(v) : 0;
+    return (size_t)(mb > 0 ? mb : 4096) << 20;
+}
+
+static sf_status ensure_workspace(sf_patch *p)
+{
+    if (p->ws || p->d != 3) return SF_OK;
+    const size_t need = assemble_workspace_bytes(p->view, 2, Prec::F64, workspace_cap());
+    hipError_t e = hipMalloc(&p->ws, need);
+    if (e != hipSuccess) {
+        p->ws = nullptr;
+        return hip_fail(p->ctx, e, "assembly workspace allocation");
+    }
+    p->ws_bytes = need;
+    return SF_OK;
+}
+
 static sf_status assemble_into(sf_patch *p, unsigned ops, int pi, double *vm, double *vs, hipStream_t s)
 {
     for (int oi = 0; oi < 2; ++oi) {
         if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
         double *dst = oi == 0 ? vm : vs;
-        hipError_t e = launch_assemble(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], dst, s);
+        hipError_t e = launch_assemble(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], dst, p->ws,
+                                       p->ws_bytes, s);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly kernel");
     }
     return SF_OK;
@@ -367,8 +397,8 @@ sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, 
     sf_status st = check_ready(p, ops, prec, pi);
     if (st != SF_OK) return st;
     if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(p->ctx, SF_EINVAL, "null output");
-    if (!assemble_supported(p->d, p->P))
-        return fail(p->ctx, SF_EUNSUPPORTED, "assembly for d = 3 is built for orders 2..6");
+    st = ensure_workspace(p);
+    if (st != SF_OK) return st;
     return assemble_into(p, ops, pi, vm, vs, p->ctx->stream);
 }
 
@@ -504,8 +534,8 @@ sf_status sf_batch_assemble(sf_batch *b, unsigned ops, sf_precision prec, int64_
     for (sf_patch *p : b->patches) {
         sf_status st = check_ready(p, ops, prec, pi);
         if (st != SF_OK) return st;
-        if (!assemble_supported(p->d, p->P))
-            return fail(b->ctx, SF_EUNSUPPORTED, "assembly for d = 3 is built for orders 2..6");
+        st = ensure_workspace(p);
+        if (st != SF_OK) return st;
     }
     return run_graph(b, 0, ops, pi, rp, ci, (ops & SF_MASS) ? vm : nullptr, (ops & SF_STIFF) ? vs : nullptr,
                      record_assemble);

@@ -56,10 +56,12 @@ def test_small_2d_identity_16x16_p3():
 
 
 @pytest.mark.parametrize("K,p", [((9, 19, 21), 2), ((6, 15, 17), 3), ((4, 9, 17), 4), ((2, 6, 17), 5),
-                                 ((1, 5, 17), 6)])
+                                 ((1, 5, 17), 6), ((60, 5, 7), 2), ((45, 4, 9), 3), ((25, 4, 9), 4),
+                                 ((14, 3, 6), 5), ((9, 2, 7), 6)])
 def test_3d_full_parity_several_tiles(K, p):
-    """Several assembly boxes in directions 2 and 3 (ragged last ones) and
-    apply tiles with ragged edges, perturbed geometry, variable coefficient."""
+    """Several direction-1 row tiles of the level-1/2 kernel and several
+    direction-3 row segments of the level-3 kernel (ragged last ones), apply
+    tiles with ragged edges, perturbed geometry, variable coefficient."""
     kn, ctrl = inputs.perturbed_geometry(K, p, seed=1)
     _full_parity(kn, p, ctrl, ("sinprod", 0.5))
 
@@ -83,22 +85,21 @@ def test_2d_perturbed(K, p):
 
 
 @pytest.mark.parametrize("K,p", [((2, 3, 2), 7), ((1, 2, 2), 8), ((1, 1, 2), 9)])
-def test_3d_high_order_apply(K, p):
-    """Orders 7-9: the geometry step and the apply (d = 3 assembly is built
-    for orders 2..6 and reports SF_EUNSUPPORTED above)."""
+def test_3d_high_order(K, p):
+    """Orders 7-9: geometry step, assembly and apply."""
     kn, ctrl = inputs.perturbed_geometry(K, p, seed=3)
-    P = oracle.Problem(kn, p, ctrl, ("sinprod", 0.5))
-    x = inputs.random_vector(P.N, 1)
-    with GpuPatch(kn, p, ctrl, ("sinprod", 0.5)) as g:
-        g.prepare()
-        for op in (sf.SF_MASS, sf.SF_STIFF):
-            rp, ci, v = P.assemble(op)
-            A = oracle.csr_to_dense(rp, ci, v, P.N)
-            y = g.apply(op, x)
-            assert err_y(y, A @ x, np.abs(A) @ np.abs(x)) <= TOL64
-        with pytest.raises(sf.SfError) as e:
-            g.assemble(sf.SF_STIFF)
-        assert e.value.status == sf.SF_EUNSUPPORTED
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5))
+
+
+@pytest.mark.parametrize("K,p,mb", [((6, 7, 13), 3, 1), ((3, 4, 11), 5, 1), ((30, 20, 9), 2, 1)])
+def test_3d_assembly_in_chunks(monkeypatch, K, p, mb):
+    """A workspace cap far below the patch's level-2 partials forces chunks of
+    element layers in direction 3 (down to the minimum of p - 1 layers);
+    entries that straddle two chunks are summed across them."""
+    monkeypatch.setenv("SFIGA_WORKSPACE_MB", str(mb))
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=12)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5))
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP32, tol=TOL32)
 
 
 def test_mass_and_stiffness_share_pattern_and_assembly_is_deterministic():
