@@ -27,6 +27,32 @@ sys.path.insert(0, ROOT)
 METRIC = "matrix-free apply GDoF/s + assembly Gnnz/s, mixed vs FP64 at stated rel. error"
 PEAK_FP64_TFLOPS = 78.6          # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_assembly_d3_48_p4_fp64.txt")
+
+
+def measured_traffic(source):
+    """HBM bytes of one assembly call from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE of its kernels, each scaled by the same counter
+    on a plain copy of known size); None if the kernels changed since."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != h:
+            return None
+        cb = float(kv["copy_bytes"])
+        ff = float(kv["copy_fetch_kib"]) * 1024 / cb
+        wf = float(kv["copy_write_kib"]) * 1024 / cb
+        fetch = sum(float(kv[k]) for k in kv if k.endswith("_fetch_kib") and not k.startswith("copy"))
+        write = sum(float(kv[k]) for k in kv if k.endswith("_write_kib") and not k.startswith("copy"))
+        return (fetch / ff + write / wf) * 1024
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def nnz1(N, p):
@@ -70,6 +96,8 @@ def parse():
     ap.add_argument("--cpu-sample-elements", type=int, default=48,
                     help="elements per direction of the patch the oracle assembles for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain device copy of %d bytes first (scale factor for HBM counters)" % COPY_BYTES)
     return ap.parse_args()
 
 
@@ -103,38 +131,41 @@ def main():
     x = torch.as_tensor(w["x"]).cuda()
     y = torch.empty(N, dtype=torch.float64, device="cuda")
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    stage_ms = np.zeros(4)
-
-    def step(record):
-        if record:
+    def step(ev):
+        if ev:
             ev[0].record(stream)
         sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, prec)
-        if record:
+        if ev:
             ev[1].record(stream)
         sf.sf_csr_pattern(ctx, h, rp, ci)
-        if record:
+        if ev:
             ev[2].record(stream)
         sf.sf_assemble(ctx, h, sf.SF_STIFF, prec, val_stiff=vals)
-        if record:
+        if ev:
             ev[3].record(stream)
         sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
-        if record:
+        if ev:
             ev[4].record(stream)
 
+    if args.calibrate_copy:
+        # plain device copy of known size, for scaling the HBM counters of a profiled run
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
-        step(False)
+        step(None)
+    # HIP events on the library's stream (torch's current stream, handed to the context)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        # per-stage durations from HIP events on the library's stream
-        ev[4].synchronize()
-        stage_ms += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    for k in range(args.steps):
+        step(evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) / args.steps * 1e3
-    stage_ms /= args.steps
+    stage_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(axis=0)
     geom_ms, pat_ms, asm_ms, app_ms = stage_ms.tolist()
 
     fl_asm = assembly_flops(K, p, "stiff")
@@ -144,9 +175,12 @@ def main():
     asm_bytes = c_bytes + nnz * 8
     app_bytes = c_bytes + 2 * N * 8
     asm_tflops = fl_asm / (asm_ms * 1e-3) / 1e12
-    roofline = {"kernel": "asm3d_kernel (Algorithm 1, levels 1-3)", "bound": "alu", "achieved": asm_tflops,
+    traffic = measured_traffic(os.path.join(ROOT, "paper_1809_05471_amd", "csrc", "assemble.hip")) \
+        if (K, p, prec) == ((48, 48, 48), 4, sf.SF_FP64) else None
+    roofline = {"kernel": "assembly (asm12_kernel levels 1-2 + asm3_kernel level 3, one sf_assemble call)",
+                "bound": "alu", "achieved": asm_tflops,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": asm_tflops / PEAK_FP64_TFLOPS,
-                "traffic": None,
+                "traffic": traffic,
                 "algorithmic_flops": fl_asm, "algorithmic_bytes": asm_bytes,
                 "achieved_GBs": asm_bytes / (asm_ms * 1e-3) / 1e9}
     out = {

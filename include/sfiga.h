@@ -26,10 +26,9 @@
  * explicit zeros included, columns ascending; it is shared by the mass and
  * stiffness matrices (Note after the definition of NZ).
  *
- * Supported: d = 1, 2, 3; one order p in 2..9 for all directions (apply and
- * the geometry step), p in 2..6 for d = 3 assembly; open knot vectors with
- * simple interior knots (maximal smoothness), any spacing.  Other inputs
- * return SF_EUNSUPPORTED.
+ * Supported: d = 1, 2, 3; one order p in 2..9 for all directions; open knot
+ * vectors with simple interior knots (maximal smoothness), any spacing.
+ * Other inputs return SF_EUNSUPPORTED.
  *
  * Memory and streams.  Every pointer documented as "device" is HIP device
  * memory owned by the caller (typically a torch tensor).  The library owns
@@ -167,7 +166,11 @@ sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col
  * dev_val_stiff, device [nnz] FP64 (the pointer of an operator not in ops
  * is ignored).  Needs a prior sf_patch_prepare of those operators at
  * `prec`.  Overwrites the outputs.  Deterministic: no atomics, fixed
- * summation order.  Asynchronous. */
+ * summation order.  Asynchronous.  For d = 3 the first call allocates the
+ * patch's level-2 workspace (the partial sums after Algorithm 1's second
+ * level; at most SFIGA_WORKSPACE_MB MiB, default 4096, larger patches run
+ * in chunks of element layers); it is freed by sf_patch_destroy.  Returns
+ * SF_ENOMEM if that allocation fails. */
 sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
                       double *dev_val_mass, double *dev_val_stiff);
 
