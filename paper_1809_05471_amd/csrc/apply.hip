@@ -27,9 +27,9 @@ struct STile {
 };
 
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
-                                                              const double *__restrict__ x, double *__restrict__ y,
-                                                              int LZ)
+__device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__restrict__ C,
+                                              const double *__restrict__ x, double *__restrict__ y, int LZ, int bx,
+                                              int by, int bz)
 {
     using TL = STile<P>;
     constexpr int E = TL::E, NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
@@ -52,8 +52,8 @@ __global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, con
     CT *t3B = t2D + E * PP, *t3D = t3B + PP;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
-    const int e1b = blockIdx.x * E, e2b = blockIdx.y * E;
-    const int e3a = blockIdx.z * LZ;
+    const int e1b = bx * E, e2b = by * E;
+    const int e3a = bz * LZ;
     const int e3z = (e3a + LZ < d2.K ? e3a + LZ : d2.K) - 1;      // last layer
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -264,6 +264,30 @@ __global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, con
 
 // d = 1, 2: one thread per element, element-local sum factorization,
 // atomics into y.
+
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
+                                                              const double *__restrict__ x, double *__restrict__ y,
+                                                              int LZ)
+{
+    apply3d_block<P, STIFF, CT>(pv, C, x, y, LZ, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Persistent form over the concatenated per-patch grids of a batch.
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__(STile<P>::NT) void apply3d_persistent(TaskList tl)
+{
+    for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
+        const int t = task_of(tl.off, tl.ntask, it);
+        const BatchTask &T = tl.tasks[t];
+        const int64_t l = it - tl.off[t];
+        const int bx = (int)(l % T.gx);
+        const int64_t r = l / T.gx;
+        apply3d_block<P, STIFF, CT>(T.pv, (const CT *)T.C, T.x, T.out, T.arg, bx, (int)(r % T.gy), (int)(r / T.gy));
+        __syncthreads();   // LDS of the next block
+    }
+}
+
 template <int DIM, int P, bool STIFF, typename CT>
 __global__ void apply_small_kernel(PatchView pv, const CT *__restrict__ C, const double *__restrict__ x,
                                    double *__restrict__ y)
@@ -332,29 +356,58 @@ __global__ void apply_small_kernel(PatchView pv, const CT *__restrict__ C, const
 }
 
 template <int P, bool STIFF, typename CT>
+static size_t apply3d_lds()
+{
+    using TL = STile<P>;
+    constexpr int NF = STIFF ? 3 : 1;
+    constexpr int NXY = TL::NX * TL::NY;
+    constexpr int SA = (2 * P * NXY > NF * P * TL::TY * TL::TX) ? 2 * P * NXY : NF * P * TL::TY * TL::TX;
+    return sizeof(CT) * (size_t)(2 * P * NXY + SA + NF * P * TL::TY * TL::NX + 4 * TL::E * P * P + 2 * P * P);
+}
+
+template <int P> static int apply_tile_elems() { return STile<P>::E; }
+
+void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &LZ)
+{
+    int E = 0;
+    switch (pv.P) {
+    case 2: E = apply_tile_elems<2>(); break;
+    case 3: E = apply_tile_elems<3>(); break;
+    case 4: E = apply_tile_elems<4>(); break;
+    case 5: E = apply_tile_elems<5>(); break;
+    case 6: E = apply_tile_elems<6>(); break;
+    case 7: E = apply_tile_elems<7>(); break;
+    case 8: E = apply_tile_elems<8>(); break;
+    default: E = apply_tile_elems<9>(); break;
+    }
+    gx = (pv.dir[0].K + E - 1) / E;
+    gy = (pv.dir[1].K + E - 1) / E;
+    if (lz <= 0) {
+        // layers per workgroup: long enough to amortise the window start-up,
+        // short enough to give every CU a few workgroups
+        lz = (int)((int64_t)gx * gy * pv.dir[2].K / 2048);
+        lz = lz < 2 ? 2 : (lz > 16 ? 16 : lz);
+    }
+    LZ = lz;
+    gz = (pv.dir[2].K + LZ - 1) / LZ;
+}
+
+template <int P, bool STIFF, typename CT>
 static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double *x, double *y, hipStream_t s)
 {
     if (pv.d == 3) {
-        using TL = STile<P>;
-        constexpr int NF = STIFF ? 3 : 1;
-        constexpr int NXY = TL::NX * TL::NY;
-        constexpr int SA = (2 * P * NXY > NF * P * TL::TY * TL::TX) ? 2 * P * NXY : NF * P * TL::TY * TL::TX;
-        const size_t lds = sizeof(CT) * (size_t)(2 * P * NXY + SA + NF * P * TL::TY * TL::NX + 4 * TL::E * P * P +
-                                                 2 * P * P);
-        static size_t lds_set = 0;
-        if (lds > lds_set) {
+        const size_t lds = apply3d_lds<P, STIFF, CT>();
+        static bool lds_set = false;
+        if (!lds_set) {
             hipError_t e = hipFuncSetAttribute((const void *)apply3d_kernel<P, STIFF, CT>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            lds_set = lds;
+            lds_set = true;
         }
-        const int gx = (pv.dir[0].K + TL::E - 1) / TL::E, gy = (pv.dir[1].K + TL::E - 1) / TL::E;
-        // layers per workgroup: long enough to amortise the window start-up,
-        // short enough to give every CU a few workgroups
-        int LZ = (int)((int64_t)gx * gy * pv.dir[2].K / 2048);
-        LZ = LZ < 2 ? 2 : (LZ > 16 ? 16 : LZ);
-        dim3 grid(gx, gy, (pv.dir[2].K + LZ - 1) / LZ);
-        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), grid, dim3(TL::NT), lds, s, pv, C, x, y, LZ);
+        int gx, gy, gz, LZ;
+        apply_blocks(pv, 0, gx, gy, gz, LZ);
+        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, x, y,
+                           LZ);
     } else {
         int64_t nel = (int64_t)pv.dir[0].K * pv.dir[1].K;
         int64_t nb = (nel + 127) / 128;
@@ -364,6 +417,47 @@ static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double 
             hipLaunchKernelGGL((apply_small_kernel<1, P, STIFF, CT>), dim3((unsigned)nb), dim3(128), 0, s, pv, C, x, y);
     }
     return hipGetLastError();
+}
+
+template <int P, bool STIFF, typename CT>
+static hipError_t launch_apply_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
+{
+    const size_t lds = apply3d_lds<P, STIFF, CT>();
+    static bool lds_set = false;
+    if (!lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)apply3d_persistent<P, STIFF, CT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
+    hipLaunchKernelGGL((apply3d_persistent<P, STIFF, CT>), dim3(nblocks), dim3(STile<P>::NT), lds, s, tl);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_apply_batch_p(const TaskList &tl, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    if (prec == Prec::F64)
+        return op == 2 ? launch_apply_batch_t<P, true, double>(tl, nblocks, s)
+                       : launch_apply_batch_t<P, false, double>(tl, nblocks, s);
+    return op == 2 ? launch_apply_batch_t<P, true, float>(tl, nblocks, s)
+                   : launch_apply_batch_t<P, false, float>(tl, nblocks, s);
+}
+
+hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    if (tl.nitems == 0) return hipSuccess;
+    switch (P) {
+    case 2: return launch_apply_batch_p<2>(tl, op, prec, nblocks, s);
+    case 3: return launch_apply_batch_p<3>(tl, op, prec, nblocks, s);
+    case 4: return launch_apply_batch_p<4>(tl, op, prec, nblocks, s);
+    case 5: return launch_apply_batch_p<5>(tl, op, prec, nblocks, s);
+    case 6: return launch_apply_batch_p<6>(tl, op, prec, nblocks, s);
+    case 7: return launch_apply_batch_p<7>(tl, op, prec, nblocks, s);
+    case 8: return launch_apply_batch_p<8>(tl, op, prec, nblocks, s);
+    case 9: return launch_apply_batch_p<9>(tl, op, prec, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int P>

@@ -111,11 +111,11 @@ __device__ __forceinline__ int comp3(int i, int j)
     return a == 0 ? (b == 1 ? 3 : 4) : 5;
 }
 
-// Levels 1 and 2 for the planes x3 in [q3base, q3base + gridDim.y).
+// Levels 1 and 2 of plane x3 = q3base + by for the tile bx of rows m1.
 // A2 layout: [plane - q3base][g][m2][m1][c2][c1], c = n - m + p - 1.
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
-                                                                        CT *__restrict__ A2, int q3base, int T1r)
+__device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__restrict__ C, CT *__restrict__ A2,
+                                            int q3base, int T1r, int bx, int by)
 {
     using S = A12Shape<P, STIFF>;
     constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
@@ -129,10 +129,10 @@ __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchVi
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1];
     const int tid = threadIdx.x;
-    const int b1 = blockIdx.x * T1r;                    // first row m1 of the tile
+    const int b1 = bx * T1r;                    // first row m1 of the tile
     const int nrow1 = min(T1r, d0.N - b1);
     const int eb1 = b1 - P + 1;                         // first direction-1 element touching the tile
-    const int pl = blockIdx.y;
+    const int pl = by;
     const int q3 = q3base + pl;
     const int Q0 = d0.Q, Q1 = d1.Q, N1 = d0.N, N2 = d1.N, K1 = d0.K, K2 = d1.K;
     const int64_t rowsz = (int64_t)N1 * WW;             // one row m2 of A2
@@ -347,24 +347,31 @@ __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchVi
     }
 }
 
-// Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
-// segments seg0 + blockIdx.z (length L each).  One thread per level-2
-// entry (m1, n1, m2 = blockIdx.y, n2).
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__restrict__ A2, double *__restrict__ vals,
-                                                   int s0, int s1, int L, int seg0)
+__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
+                                                                        CT *__restrict__ A2, int q3base, int T1r)
+{
+    asm12_block<P, STIFF, CT>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
+}
+
+// Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
+// segment seg0 + bz (length L).  One thread per level-2 entry
+// (m1, n1, m2 = by, n2); block bx covers 256 entries of the row m2.
+template <int P, bool STIFF, typename CT>
+__device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__restrict__ A2, double *__restrict__ vals,
+                                           int s0, int s1, int L, int seg0, int bx, int by, int bz)
 {
     constexpr int W = 2 * P - 1, WW = W * W, NG = STIFF ? 4 : 1;
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
     const int N1 = d0.N, N2 = d1.N;
     const int64_t rowsz = (int64_t)N1 * WW;
-    const int it = blockIdx.x * 256 + threadIdx.x;
+    const int it = bx * 256 + threadIdx.x;
     if (it >= rowsz) return;
-    const int m2 = blockIdx.y;
+    const int m2 = by;
     const int c1 = it % W, c2 = (it / W) % W, m1 = it / WW;
     const int n1 = m1 + c1 - P + 1, n2 = m2 + c2 - P + 1;
     if (n1 < 0 || n1 >= N1 || n2 < 0 || n2 >= N2) return;
-    const int a3 = (seg0 + blockIdx.z) * L;
+    const int a3 = (seg0 + bz) * L;
     const int ebeg = max(s0, a3 - P + 1), eend = min(s1 - 1, a3 + L - 1);
     if (ebeg > eend) return;
 
@@ -448,6 +455,13 @@ __global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__res
 #pragma unroll
         for (int k = 0; k < P; ++k) w[P - 1][k] = w[k][P - 1] = 0.0;
     }
+}
+
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__restrict__ A2, double *__restrict__ vals,
+                                                   int s0, int s1, int L, int seg0)
+{
+    asm3_block<P, STIFF, CT>(pv, A2, vals, s0, s1, L, seg0, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------------ d <= 2
@@ -561,28 +575,75 @@ size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t c
     return layers * per_layer;
 }
 
+bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_bytes)
+{
+    return pv.d == 3 && a2_chunk(pv, op, prec, ws_bytes) == pv.dir[2].K;
+}
+
+template <int P> static int a12_rows() { return A12Cfg<P>::T1; }
+
+int asm12_max_rows(int P)
+{
+    switch (P) {
+    case 2: return a12_rows<2>();
+    case 3: return a12_rows<3>();
+    case 4: return a12_rows<4>();
+    case 5: return a12_rows<5>();
+    case 6: return a12_rows<6>();
+    case 7: return a12_rows<7>();
+    case 8: return a12_rows<8>();
+    default: return a12_rows<9>();
+    }
+}
+
+void asm12_blocks(const PatchView &pv, int t1, int &gx, int &gy, int &T1r)
+{
+    const int tmax = asm12_max_rows(pv.P);
+    if (t1 <= 0 || t1 > tmax) t1 = tmax;
+    const int N1 = pv.dir[0].N;
+    const int ntile = (N1 + t1 - 1) / t1;
+    T1r = (N1 + ntile - 1) / ntile;                          // balanced tiles
+    gx = ntile;
+    gy = pv.dir[2].Q;
+}
+
+void asm3_blocks(const PatchView &pv, int seg, int &gx, int &gy, int &gz, int &L)
+{
+    const int W = 2 * pv.P - 1, N3 = pv.dir[2].N;
+    const int nseg = (N3 + (seg > 0 ? seg : 16) - 1) / (seg > 0 ? seg : 16);
+    L = (N3 + nseg - 1) / nseg;
+    gx = (int)(((int64_t)pv.dir[0].N * W * W + 255) / 256);
+    gy = pv.dir[1].N;
+    gz = nseg;
+}
+
+template <int P, bool STIFF, typename CT>
+static hipError_t set_asm12_lds(const void *fn)
+{
+    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <int P, bool STIFF, typename CT>
 static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, void *ws, size_t ws_bytes,
                                hipStream_t s)
 {
     using S = A12Shape<P, STIFF>;
     const size_t lds = a12_lds_bytes<P, STIFF, CT>();
-    static size_t lds_set = 0;     // per instantiation: raise the dynamic LDS limit once
-    if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)asm12_kernel<P, STIFF, CT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static bool lds_set = false;     // per instantiation: raise the dynamic LDS limit once
+    if (!lds_set) {
+        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_kernel<P, STIFF, CT>);
         if (e != hipSuccess) return e;
-        lds_set = lds;
+        lds_set = true;
     }
     const int op = STIFF ? 2 : 1;
     const Prec prec = sizeof(CT) == sizeof(double) ? Prec::F64 : Prec::F32;
     const int chunk = a2_chunk(pv, op, prec, ws_bytes);
     if (chunk == 0 || !ws) return hipErrorInvalidValue;
-    const int N1 = pv.dir[0].N, N2 = pv.dir[1].N, N3 = pv.dir[2].N, K3 = pv.dir[2].K;
-    const int ntile = (N1 + S::T1 - 1) / S::T1;
-    const int T1r = (N1 + ntile - 1) / ntile;               // balanced tiles of at most T1 rows
-    const int nseg = (N3 + 15) / 16, L = (N3 + nseg - 1) / nseg;
-    const int64_t rowsz = (int64_t)N1 * S::W * S::W;
+    const int N3 = pv.dir[2].N, K3 = pv.dir[2].K;
+    int ntile, nplane, T1r, gx3, gy3, nseg, L;
+    asm12_blocks(pv, 0, ntile, nplane, T1r);
+    asm3_blocks(pv, 0, gx3, gy3, nseg, L);
     CT *A2 = static_cast<CT *>(ws);
     for (int s0 = 0; s0 < K3; s0 += chunk) {
         const int s1 = s0 + chunk < K3 ? s0 + chunk : K3;
@@ -590,10 +651,105 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
                            s0 * P, T1r);
         const int last_row = s1 + P - 2 < N3 - 1 ? s1 + P - 2 : N3 - 1;
         const int seg0 = s0 / L, seg1 = last_row / L;
-        hipLaunchKernelGGL((asm3_kernel<P, STIFF, CT>), dim3((unsigned)((rowsz + 255) / 256), N2, seg1 - seg0 + 1),
-                           dim3(256), 0, s, pv, (const CT *)A2, vals, s0, s1, L, seg0);
+        hipLaunchKernelGGL((asm3_kernel<P, STIFF, CT>), dim3(gx3, gy3, seg1 - seg0 + 1), dim3(256), 0, s, pv,
+                           (const CT *)A2, vals, s0, s1, L, seg0);
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched
+
+// Persistent forms: each workgroup takes blocks it = blockIdx.x, + gridDim.x,
+// ... of the concatenated per-patch grids (every patch in one chunk).
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_persistent(TaskList tl)
+{
+    for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
+        const int t = task_of(tl.off, tl.ntask, it);
+        const BatchTask &T = tl.tasks[t];
+        const int64_t l = it - tl.off[t];
+        asm12_block<P, STIFF, CT>(T.pv, (const CT *)T.C, (CT *)T.ws, 0, T.arg, (int)(l % T.gx), (int)(l / T.gx));
+        __syncthreads();   // LDS of the next block
+    }
+}
+
+template <int P, bool STIFF, typename CT>
+__global__ __launch_bounds__(256) void asm3_persistent(TaskList tl)
+{
+    for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
+        const int t = task_of(tl.off, tl.ntask, it);
+        const BatchTask &T = tl.tasks[t];
+        const int64_t l = it - tl.off[t];
+        const int bx = (int)(l % T.gx);
+        const int64_t r = l / T.gx;
+        asm3_block<P, STIFF, CT>(T.pv, (const CT *)T.ws, T.out, 0, T.pv.dir[2].K, T.arg, 0, bx, (int)(r % T.gy),
+                                 (int)(r / T.gy));
+    }
+}
+
+template <int P, bool STIFF, typename CT>
+static hipError_t launch_asm12_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
+{
+    static bool lds_set = false;
+    if (!lds_set) {
+        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_persistent<P, STIFF, CT>);
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
+    constexpr int NT = A12Shape<P, STIFF>::NT;
+    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
+    hipLaunchKernelGGL((asm12_persistent<P, STIFF, CT>), dim3(nblocks), dim3(NT), lds, s, tl);
+    return hipGetLastError();
+}
+
+template <int P, bool STIFF, typename CT>
+static hipError_t launch_asm3_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((asm3_persistent<P, STIFF, CT>), dim3(nblocks), dim3(256), 0, s, tl);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_batch_p(int which, const TaskList &tl, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    if (which == 0) {
+        if (prec == Prec::F64)
+            return op == 2 ? launch_asm12_batch_t<P, true, double>(tl, nblocks, s)
+                           : launch_asm12_batch_t<P, false, double>(tl, nblocks, s);
+        return op == 2 ? launch_asm12_batch_t<P, true, float>(tl, nblocks, s)
+                       : launch_asm12_batch_t<P, false, float>(tl, nblocks, s);
+    }
+    if (prec == Prec::F64)
+        return op == 2 ? launch_asm3_batch_t<P, true, double>(tl, nblocks, s)
+                       : launch_asm3_batch_t<P, false, double>(tl, nblocks, s);
+    return op == 2 ? launch_asm3_batch_t<P, true, float>(tl, nblocks, s)
+                   : launch_asm3_batch_t<P, false, float>(tl, nblocks, s);
+}
+
+static hipError_t launch_batch(int which, const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    if (tl.nitems == 0) return hipSuccess;
+    switch (P) {
+    case 2: return launch_batch_p<2>(which, tl, op, prec, nblocks, s);
+    case 3: return launch_batch_p<3>(which, tl, op, prec, nblocks, s);
+    case 4: return launch_batch_p<4>(which, tl, op, prec, nblocks, s);
+    case 5: return launch_batch_p<5>(which, tl, op, prec, nblocks, s);
+    case 6: return launch_batch_p<6>(which, tl, op, prec, nblocks, s);
+    case 7: return launch_batch_p<7>(which, tl, op, prec, nblocks, s);
+    case 8: return launch_batch_p<8>(which, tl, op, prec, nblocks, s);
+    case 9: return launch_batch_p<9>(which, tl, op, prec, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_asm12_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    return launch_batch(0, tl, P, op, prec, nblocks, s);
+}
+
+hipError_t launch_asm3_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s)
+{
+    return launch_batch(1, tl, P, op, prec, nblocks, s);
 }
 
 template <int P, bool STIFF, typename CT>

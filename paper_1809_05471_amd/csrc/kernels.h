@@ -50,6 +50,40 @@ __host__ __device__ inline int64_t coef_index(int d, int ncomp, int comp, int q0
     return (((int64_t)q2 * ncomp + comp) * Q1 + q1) * Q0 + q0;
 }
 
+// One patch's share of a batched launch: the arguments of the per-patch
+// kernel and its block grid.  A persistent kernel walks the blocks of all
+// tasks of one kind and order in task order (largest first).
+struct BatchTask {
+    PatchView pv;
+    const void *C;         // coefficient tensor of the operator at the precision
+    void *ws;              // level-2 workspace of the assembly
+    double *out;           // assembly values or y, offset to the patch
+    const double *x;       // apply input, offset to the patch
+    int64_t *row_ptr;      // pattern: the patch's row pointer entries
+    int32_t *col_ind;      // pattern: whole column index array
+    int64_t col_base, nnz_base;
+    int gx, gy, gz;        // blocks of the per-patch launch
+    int arg;               // rows per tile (levels 1-2), rows per segment (level 3), layers (apply)
+};
+
+struct TaskList {
+    const BatchTask *tasks;    // device
+    const int64_t *off;        // device, [ntask + 1] prefix sums of gx gy gz
+    int ntask;
+    int64_t nitems;
+};
+
+// task of block `it` (binary search in the prefix sums)
+__device__ __forceinline__ int task_of(const int64_t *off, int ntask, int64_t it)
+{
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= it) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 hipError_t launch_geometry(const PatchView &pv, const GeomOut &out, hipStream_t s);
 hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
                           int64_t col_base, int64_t nnz_base, hipStream_t s);
@@ -64,5 +98,20 @@ hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c
 // workspace of the d = 3 assembly of op at prec: whole patch if it fits in
 // cap bytes, else chunks of element layers (never fewer than p - 1)
 size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t cap);
+// true if the workspace holds the whole patch (one chunk)
+bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_bytes);
+
+// Batched (persistent) kernels of one order P; nblocks = workgroups of the
+// persistent grid.  Block shapes of one task for the tunable parameter
+// (0 = the single-patch default):
+void asm12_blocks(const PatchView &pv, int t1, int &gx, int &gy, int &T1r);   // t1: rows m1 per tile
+void asm3_blocks(const PatchView &pv, int seg, int &gx, int &gy, int &gz, int &L);  // seg: rows m3 per segment
+void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &LZ);  // lz: layers per workgroup
+int asm12_max_rows(int P);
+hipError_t launch_asm12_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);
+hipError_t launch_asm3_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);
+hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);
+hipError_t launch_rowptr_batch(const TaskList &tl, int nblocks, hipStream_t s);
+hipError_t launch_colind_batch(const TaskList &tl, int P, int nblocks, hipStream_t s);
 
 }  // namespace sfiga

@@ -7,9 +7,9 @@
 
 namespace sfiga {
 
-__global__ void row_ptr_kernel(RowIndex ri, int64_t nrows, int64_t *row_ptr, int64_t base)
+__device__ __forceinline__ void row_ptr_row(const RowIndex &ri, int64_t nrows, int64_t *row_ptr, int64_t base,
+                                            int64_t m)
 {
-    int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (m > nrows) return;
     if (m == nrows) {
         row_ptr[m] = base + ri.T[0] * (ri.d >= 2 ? ri.T[1] : 1) * (ri.d >= 3 ? ri.T[2] : 1);
@@ -22,15 +22,20 @@ __global__ void row_ptr_kernel(RowIndex ri, int64_t nrows, int64_t *row_ptr, int
     row_ptr[m] = base + row_start(ri, m0, m1, m2);
 }
 
+__global__ void row_ptr_kernel(RowIndex ri, int64_t nrows, int64_t *row_ptr, int64_t base)
+{
+    row_ptr_row(ri, nrows, row_ptr, base, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
 // One wavefront per row; lanes walk the row's (2p-1)^d band entries.  Rows
 // whose band is not clipped in any direction (the bulk) decompose the entry
 // index with the compile-time band width; clipped rows with their own lengths.
 template <int P>
-__global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int64_t col_base, int64_t nnz_base)
+__device__ __forceinline__ void col_ind_row(const RowIndex &ri, int64_t nrows, int32_t *col_ind, int64_t col_base,
+                                            int64_t nnz_base, int64_t m)
 {
     constexpr int W = 2 * P - 1;
     const int lane = threadIdx.x % 64;
-    const int64_t m = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
     if (m >= nrows) return;
     int m0 = (int)(m % ri.N[0]);
     int64_t r = m / ri.N[0];
@@ -55,6 +60,59 @@ __global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int
         const int a = t % l0, b = (t / l0) % l1, c = t / (l0 * l1);
         out[t] = (int32_t)(first + a + N0 * b + N01 * c);
     }
+}
+
+template <int P>
+__global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int64_t col_base, int64_t nnz_base)
+{
+    col_ind_row<P>(ri, nrows, col_ind, col_base, nnz_base,
+                   blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64);
+}
+
+// Persistent forms over the rows of a batch: block bx of a task covers rows
+// [256 bx, 256 bx + 256) (row pointers) or [4 bx, 4 bx + 4) (column indices).
+__global__ void row_ptr_persistent(TaskList tl)
+{
+    for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
+        const int t = task_of(tl.off, tl.ntask, it);
+        const BatchTask &T = tl.tasks[t];
+        row_ptr_row(T.pv.ri, T.pv.N, T.row_ptr, T.nnz_base, (it - tl.off[t]) * 256 + threadIdx.x);
+    }
+}
+
+template <int P>
+__global__ void col_ind_persistent(TaskList tl)
+{
+    for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
+        const int t = task_of(tl.off, tl.ntask, it);
+        const BatchTask &T = tl.tasks[t];
+        col_ind_row<P>(T.pv.ri, T.pv.N, T.col_ind, T.col_base, T.nnz_base, (it - tl.off[t]) * 4 + threadIdx.x / 64);
+    }
+}
+
+hipError_t launch_rowptr_batch(const TaskList &tl, int nblocks, hipStream_t s)
+{
+    if (tl.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(row_ptr_persistent, dim3(nblocks), dim3(256), 0, s, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_colind_batch(const TaskList &tl, int P, int nblocks, hipStream_t s)
+{
+    if (tl.nitems == 0) return hipSuccess;
+    dim3 g(nblocks), b(256);
+    switch (P) {
+    case 2: hipLaunchKernelGGL(col_ind_persistent<2>, g, b, 0, s, tl); break;
+    case 3: hipLaunchKernelGGL(col_ind_persistent<3>, g, b, 0, s, tl); break;
+    case 4: hipLaunchKernelGGL(col_ind_persistent<4>, g, b, 0, s, tl); break;
+    case 5: hipLaunchKernelGGL(col_ind_persistent<5>, g, b, 0, s, tl); break;
+    case 6: hipLaunchKernelGGL(col_ind_persistent<6>, g, b, 0, s, tl); break;
+    case 7: hipLaunchKernelGGL(col_ind_persistent<7>, g, b, 0, s, tl); break;
+    case 8: hipLaunchKernelGGL(col_ind_persistent<8>, g, b, 0, s, tl); break;
+    case 9: hipLaunchKernelGGL(col_ind_persistent<9>, g, b, 0, s, tl); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 __global__ void fill_kernel(double *y, int64_t n, double v)

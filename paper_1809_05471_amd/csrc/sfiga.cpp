@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,6 +46,7 @@ struct sf_batch {
     sf_ctx *ctx = nullptr;
     std::vector<sf_patch *> patches;
     std::vector<int64_t> row_off, nnz_off;
+    int ncu = 256;                // compute units (persistent grid = ncu x multiplier)
     // cached graphs keyed by the launch arguments
     struct Cached {
         int kind;                 // 0 assemble, 1 apply
@@ -54,6 +56,15 @@ struct sf_batch {
         hipGraphExec_t exec;
     };
     std::vector<Cached> graphs;
+    // autotuned launch parameters per (kernel, order, operator, precision):
+    // tile parameter (see *_blocks) and workgroups per compute unit
+    struct Tuned {
+        int kernel, P, op, prec;
+        int param, mult;
+        float ms;
+    };
+    std::vector<Tuned> tuned;
+    std::vector<void *> dev;      // device task lists referenced by the graphs
 };
 
 namespace {
@@ -436,6 +447,9 @@ sf_status sf_batch_create(sf_ctx *ctx, int npatch, sf_patch *const *patches, sf_
     sf_batch *b = new (std::nothrow) sf_batch;
     if (!b) return fail(ctx, SF_ENOMEM, "host allocation failed");
     b->ctx = ctx;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+        b->ncu = ncu;
     b->row_off.push_back(0);
     b->nnz_off.push_back(0);
     for (int i = 0; i < npatch; ++i) {
@@ -462,24 +476,280 @@ sf_status sf_batch_offsets(const sf_batch *b, int64_t *row_off, int64_t *nnz_off
     return SF_OK;
 }
 
-static sf_status run_graph(sf_batch *b, int kind, unsigned ops, int pi, const void *p0, const void *p1,
-                           const void *p2, const void *p3,
-                           sf_status (*record)(sf_batch *, unsigned, int, const void *, const void *, const void *,
-                                               const void *, hipStream_t))
+// ---- batched launches: persistent kernels over per-patch tasks
+
+enum { KASM12 = 0, KASM3 = 1, KAPPLY = 2, KROWPTR = 3, KCOLIND = 4 };
+
+struct HostTasks {
+    std::vector<BatchTask> t;
+    std::vector<int64_t> off;
+};
+
+// Pointers of one batched call.
+struct BatchIO {
+    int64_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    double *vals[2] = {nullptr, nullptr};   // assembly outputs: mass, stiffness
+    const double *x = nullptr;
+    double *y = nullptr;
+};
+
+static bool persistent_ok(const sf_patch *p, int kernel, int oi, int pi)
+{
+    if (kernel == KROWPTR || kernel == KCOLIND) return true;
+    if (p->d != 3) return false;
+    if (kernel == KAPPLY) return true;
+    return assemble_single_chunk(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->ws_bytes);
+}
+
+// Tasks of one kernel for the patches of order P (P = 0: all orders), largest
+// block count first so that the persistent grid ends evenly.
+static HostTasks build_tasks(const sf_batch *b, int kernel, int P, int oi, int pi, int param, const BatchIO &io)
+{
+    HostTasks h;
+    for (size_t i = 0; i < b->patches.size(); ++i) {
+        const sf_patch *p = b->patches[i];
+        if ((P && p->P != P) || !persistent_ok(p, kernel, oi, pi)) continue;
+        BatchTask T{};
+        T.pv = p->view;
+        T.C = p->C[oi][pi];
+        T.ws = p->ws;
+        const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
+        T.gy = T.gz = 1;
+        switch (kernel) {
+        case KASM12: asm12_blocks(p->view, param, T.gx, T.gy, T.arg); break;
+        case KASM3:
+            asm3_blocks(p->view, param, T.gx, T.gy, T.gz, T.arg);
+            T.out = io.vals[oi] + z0;
+            break;
+        case KAPPLY:
+            apply_blocks(p->view, param, T.gx, T.gy, T.gz, T.arg);
+            T.x = io.x + r0;
+            T.out = io.y + r0;
+            break;
+        case KROWPTR:
+            T.gx = (int)((p->view.N + 1 + 255) / 256);
+            T.row_ptr = io.rp + r0;
+            T.nnz_base = z0;
+            break;
+        default:
+            T.gx = (int)((p->view.N + 3) / 4);
+            T.col_ind = io.ci;
+            T.col_base = r0;
+            T.nnz_base = z0;
+            break;
+        }
+        h.t.push_back(T);
+    }
+    std::stable_sort(h.t.begin(), h.t.end(), [](const BatchTask &a, const BatchTask &c) {
+        return (int64_t)a.gx * a.gy * a.gz > (int64_t)c.gx * c.gy * c.gz;
+    });
+    h.off.push_back(0);
+    for (const BatchTask &T : h.t) h.off.push_back(h.off.back() + (int64_t)T.gx * T.gy * T.gz);
+    return h;
+}
+
+static hipError_t upload_tasks(const HostTasks &h, TaskList &tl, void **mem)
+{
+    tl.ntask = (int)h.t.size();
+    tl.nitems = h.off.back();
+    const size_t tb = sizeof(BatchTask) * h.t.size(), ob = sizeof(int64_t) * h.off.size();
+    *mem = nullptr;
+    hipError_t e = hipMalloc(mem, tb + ob + 16);
+    if (e != hipSuccess) return e;
+    char *base = static_cast<char *>(*mem);
+    if (tb) e = hipMemcpy(base, h.t.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + tb, h.off.data(), ob, hipMemcpyHostToDevice);
+    tl.tasks = reinterpret_cast<const BatchTask *>(base);
+    tl.off = reinterpret_cast<const int64_t *>(base + tb);
+    return e;
+}
+
+static hipError_t launch_kernel(int kernel, const TaskList &tl, int P, int oi, int pi, int nblocks, hipStream_t s)
+{
+    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
+    switch (kernel) {
+    case KASM12: return launch_asm12_batch(tl, P, oi + 1, prec, nblocks, s);
+    case KASM3: return launch_asm3_batch(tl, P, oi + 1, prec, nblocks, s);
+    case KAPPLY: return launch_apply_batch(tl, P, oi + 1, prec, nblocks, s);
+    case KROWPTR: return launch_rowptr_batch(tl, nblocks, s);
+    default: return launch_colind_batch(tl, P, nblocks, s);
+    }
+}
+
+// Autotuner: time every candidate (tile parameter x workgroups per CU) of one
+// kernel on this batch's own patches and keep the fastest.  Runs once per
+// (kernel, order, operator, precision), outside any capture; its outputs are
+// scratch (the real launch rewrites them).
+static sf_status tune(sf_batch *b, int kernel, int P, int oi, int pi, const BatchIO &io, int &param, int &mult)
+{
+    for (const sf_batch::Tuned &t : b->tuned)
+        if (t.kernel == kernel && t.P == P && t.op == oi && t.prec == pi) {
+            param = t.param;
+            mult = t.mult;
+            return SF_OK;
+        }
+    std::vector<int> params, mults = {1, 2};
+    if (kernel == KASM12) {
+        const int tmax = asm12_max_rows(P);
+        params = {tmax, (tmax + 1) / 2};
+    } else if (kernel == KASM3) {
+        params = {8, 16, 32};
+        mults = {1, 2, 4};
+    } else if (kernel == KAPPLY) {
+        params = {1, 2, 4, 8};
+    } else {
+        param = 0;
+        mult = 4;
+        return SF_OK;
+    }
+    hipStream_t s = b->ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    param = params[0];
+    mult = mults[0];
+    for (int prm : params) {
+        HostTasks h = build_tasks(b, kernel, P, oi, pi, prm, io);
+        if (h.t.empty()) break;
+        TaskList tl{};
+        void *mem = nullptr;
+        if (e == hipSuccess) e = upload_tasks(h, tl, &mem);
+        for (int m : mults) {
+            if (e != hipSuccess) break;
+            e = launch_kernel(kernel, tl, P, oi, pi, b->ncu * m, s);      // warm-up
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_kernel(kernel, tl, P, oi, pi, b->ncu * m, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                param = prm;
+                mult = m;
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(mem);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(b->ctx, e, "autotuning batched kernels");
+    b->tuned.push_back(sf_batch::Tuned{kernel, P, oi, pi, param, mult, best / 2});
+    return SF_OK;
+}
+
+struct Plan {
+    int kernel, P, oi, param, mult;
+    TaskList tl;                  // device task list (owned by the batch)
+};
+
+// Task list of one planned launch, uploaded before any capture; it stays
+// alive with the batch because captured graphs reference it.
+static sf_status prepare_launch(sf_batch *b, Plan &pl, int pi, const BatchIO &io)
+{
+    HostTasks h = build_tasks(b, pl.kernel, pl.P, pl.oi, pi, pl.param, io);
+    pl.tl = TaskList{};
+    if (h.t.empty()) return SF_OK;
+    void *mem = nullptr;
+    hipError_t e = upload_tasks(h, pl.tl, &mem);
+    if (mem) b->dev.push_back(mem);
+    return e == hipSuccess ? SF_OK : hip_fail(b->ctx, e, "batch task list");
+}
+
+// The launches of one batched call, tuned (before any capture).
+static sf_status plan_call(sf_batch *b, int kind, unsigned ops, int pi, const BatchIO &io_in, std::vector<Plan> &plan)
+{
+    std::vector<int> orders;
+    for (sf_patch *p : b->patches)
+        if (std::find(orders.begin(), orders.end(), p->P) == orders.end()) orders.push_back(p->P);
+    std::sort(orders.begin(), orders.end());
+    int param, mult;
+    if (kind == 0) {
+        plan.push_back(Plan{KROWPTR, 0, 0, 0, 4, {}});
+        for (int P : orders) plan.push_back(Plan{KCOLIND, P, 0, 0, 4, {}});
+        for (int oi = 0; oi < 2; ++oi) {
+            if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
+            for (int P : orders) {
+                for (int k : {KASM12, KASM3}) {
+                    sf_status st = tune(b, k, P, oi, pi, io_in, param, mult);
+                    if (st != SF_OK) return st;
+                    plan.push_back(Plan{k, P, oi, param, mult, {}});
+                }
+            }
+        }
+    } else {
+        const int oi = ops == SF_MASS ? 0 : 1;
+        for (int P : orders) {
+            sf_status st = tune(b, KAPPLY, P, oi, pi, io_in, param, mult);
+            if (st != SF_OK) return st;
+            plan.push_back(Plan{KAPPLY, P, oi, param, mult, {}});
+        }
+    }
+    for (Plan &pl : plan) {
+        sf_status st = prepare_launch(b, pl, pi, io_in);
+        if (st != SF_OK) return st;
+    }
+    return SF_OK;
+}
+
+// Record (or run, on the null stream) the launches of a batched call.
+static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const BatchIO &io_in,
+                             const std::vector<Plan> &plan, hipStream_t s)
+{
+    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
+    if (kind == 1) {
+        hipError_t e = launch_fill(io_in.y, b->row_off.back(), 0.0, s);
+        if (e != hipSuccess) return hip_fail(b->ctx, e, "fill");
+    }
+    for (const Plan &pl : plan) {
+        if (pl.tl.nitems == 0) continue;
+        hipError_t e = launch_kernel(pl.kernel, pl.tl, pl.P, pl.oi, pi, b->ncu * pl.mult, s);
+        if (e != hipSuccess) return hip_fail(b->ctx, e, "batched kernel");
+    }
+    // patches the persistent kernels do not take (d < 3, or assembled in chunks)
+    for (size_t i = 0; i < b->patches.size(); ++i) {
+        sf_patch *p = b->patches[i];
+        const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
+        for (int oi = 0; oi < 2; ++oi) {
+            if (kind == 0 && !(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
+            if (kind == 1 && oi != (ops == SF_MASS ? 0 : 1)) continue;
+            const int kernel = kind == 0 ? KASM12 : KAPPLY;
+            if (persistent_ok(p, kernel, oi, pi)) continue;
+            hipError_t e;
+            if (kind == 0) {
+                double *dst = io_in.vals[oi] + z0;
+                e = launch_assemble(p->view, oi + 1, prec, p->C[oi][pi], dst, p->ws, p->ws_bytes, s);
+            } else {
+                e = launch_apply(p->view, oi + 1, prec, p->C[oi][pi], io_in.x + r0, io_in.y + r0, s);
+            }
+            if (e != hipSuccess) return hip_fail(b->ctx, e, "per-patch kernel");
+        }
+    }
+    return SF_OK;
+}
+
+static sf_status run_call(sf_batch *b, int kind, unsigned ops, int pi, const BatchIO &io, const void *k0,
+                          const void *k1, const void *k2, const void *k3)
 {
     sf_ctx *ctx = b->ctx;
     hipStream_t s = ctx->stream;
     for (auto &c : b->graphs)
-        if (c.kind == kind && c.ops == ops && c.prec == pi && c.p0 == p0 && c.p1 == p1 && c.p2 == p2 && c.p3 == p3) {
+        if (c.kind == kind && c.ops == ops && c.prec == pi && c.p0 == k0 && c.p1 == k1 && c.p2 == k2 && c.p3 == k3) {
             hipError_t e = hipGraphLaunch(c.exec, s);
             return e == hipSuccess ? SF_OK : hip_fail(ctx, e, "graph launch");
         }
+    std::vector<Plan> plan;
+    sf_status st = plan_call(b, kind, ops, pi, io, plan);
+    if (st != SF_OK) return st;
     // a capture needs a non-default stream
-    if (!s) return record(b, ops, pi, p0, p1, p2, p3, s);
+    if (!s) return record_call(b, kind, ops, pi, io, plan, s);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
-    sf_status st = record(b, ops, pi, p0, p1, p2, p3, s);
+    st = record_call(b, kind, ops, pi, io, plan, s);
     e = hipStreamEndCapture(s, &graph);
     if (st != SF_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -490,37 +760,9 @@ static sf_status run_graph(sf_batch *b, int kind, unsigned ops, int pi, const vo
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
-    b->graphs.push_back(sf_batch::Cached{kind, ops, pi, p0, p1, p2, p3, exec});
+    b->graphs.push_back(sf_batch::Cached{kind, ops, pi, k0, k1, k2, k3, exec});
     e = hipGraphLaunch(exec, s);
     return e == hipSuccess ? SF_OK : hip_fail(ctx, e, "graph launch");
-}
-
-static sf_status record_assemble(sf_batch *b, unsigned ops, int pi, const void *rp, const void *ci, const void *vm,
-                                 const void *vs, hipStream_t s)
-{
-    for (size_t i = 0; i < b->patches.size(); ++i) {
-        sf_patch *p = b->patches[i];
-        const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
-        hipError_t e = launch_pattern(p->view, (int64_t *)rp, (int32_t *)ci, r0, r0, z0, s);
-        if (e != hipSuccess) return hip_fail(b->ctx, e, "pattern kernels");
-        sf_status st = assemble_into(p, ops, pi, vm ? (double *)vm + z0 : nullptr, vs ? (double *)vs + z0 : nullptr, s);
-        if (st != SF_OK) return st;
-    }
-    return SF_OK;
-}
-
-static sf_status record_apply(sf_batch *b, unsigned op, int pi, const void *x, const void *y, const void *,
-                              const void *, hipStream_t s)
-{
-    int oi = op == SF_MASS ? 0 : 1;
-    for (size_t i = 0; i < b->patches.size(); ++i) {
-        sf_patch *p = b->patches[i];
-        const int64_t r0 = b->row_off[i];
-        hipError_t e = launch_apply(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi],
-                                    (const double *)x + r0, (double *)y + r0, s);
-        if (e != hipSuccess) return hip_fail(b->ctx, e, "apply kernel");
-    }
-    return SF_OK;
 }
 
 sf_status sf_batch_assemble(sf_batch *b, unsigned ops, sf_precision prec, int64_t *rp, int32_t *ci, double *vm,
@@ -537,8 +779,12 @@ sf_status sf_batch_assemble(sf_batch *b, unsigned ops, sf_precision prec, int64_
         st = ensure_workspace(p);
         if (st != SF_OK) return st;
     }
-    return run_graph(b, 0, ops, pi, rp, ci, (ops & SF_MASS) ? vm : nullptr, (ops & SF_STIFF) ? vs : nullptr,
-                     record_assemble);
+    BatchIO io;
+    io.rp = rp;
+    io.ci = ci;
+    io.vals[0] = (ops & SF_MASS) ? vm : nullptr;
+    io.vals[1] = (ops & SF_STIFF) ? vs : nullptr;
+    return run_call(b, 0, ops, pi, io, rp, ci, io.vals[0], io.vals[1]);
 }
 
 sf_status sf_batch_apply(sf_batch *b, unsigned op, sf_precision prec, const double *x, double *y)
@@ -552,7 +798,10 @@ sf_status sf_batch_apply(sf_batch *b, unsigned op, sf_precision prec, const doub
         sf_status st = check_ready(p, op, prec, pi);
         if (st != SF_OK) return st;
     }
-    return run_graph(b, 1, op, pi, x, y, nullptr, nullptr, record_apply);
+    BatchIO io;
+    io.x = x;
+    io.y = y;
+    return run_call(b, 1, op, pi, io, x, y, nullptr, nullptr);
 }
 
 void sf_batch_destroy(sf_batch *b)
@@ -560,6 +809,7 @@ void sf_batch_destroy(sf_batch *b)
     if (!b) return;
     (void)hipStreamSynchronize(b->ctx->stream);
     for (auto &c : b->graphs) (void)hipGraphExecDestroy(c.exec);
+    for (void *m : b->dev) (void)hipFree(m);
     delete b;
 }
 

@@ -9,6 +9,7 @@ import numpy as np
 import paper_1809_05471_amd as sf
 
 _CTX = None
+_SIDE = None
 
 
 def torch_cuda():
@@ -25,20 +26,33 @@ def ctx():
     return _CTX
 
 
+def side_ctx():
+    """A second context on a torch side stream (default priority): its
+    batched calls are captured into HIP graphs and replayed."""
+    global _SIDE
+    if _SIDE is None:
+        torch = torch_cuda()
+        torch.cuda.init()
+        stream = torch.cuda.Stream()
+        _SIDE = (sf.sf_ctx_create(0, stream.cuda_stream), stream)
+    return _SIDE
+
+
 COEF_KIND = {"const": sf.SF_COEF_CONST, "sinprod": sf.SF_COEF_SINPROD}
 
 
 class GpuPatch:
-    def __init__(self, knots, p, ctrl, coef=("const", 1.0)):
+    def __init__(self, knots, p, ctrl, coef=("const", 1.0), context=None):
         self.d = len(knots)
         self.p = p
-        self.h = sf.sf_patch_create(ctx(), self.d, p, knots, ctrl)
+        self.ctx = context if context is not None else ctx()
+        self.h = sf.sf_patch_create(self.ctx, self.d, p, knots, ctrl)
         self.N, self.nnz, self.Q = sf.sf_patch_info(self.h)
         kind, val = coef
-        sf.sf_patch_set_coef(ctx(), self.h, sf.SF_STIFF, COEF_KIND[kind], val)
+        sf.sf_patch_set_coef(self.ctx, self.h, sf.SF_STIFF, COEF_KIND[kind], val)
 
     def prepare(self, ops=sf.SF_MASS | sf.SF_STIFF, prec=sf.SF_FP64):
-        sf.sf_patch_prepare(ctx(), self.h, ops, prec)
+        sf.sf_patch_prepare(self.ctx, self.h, ops, prec)
 
     def pattern(self):
         torch = torch_cuda()

@@ -204,53 +204,61 @@ def test_order_sweep_apply_sampled(p):
         _sampled_parity(w, (sf.SF_STIFF,), prec=sf.SF_FP32, tol=TOL32, nrandom=4, assemble=False, coarse=True)
 
 
-def test_batched_patches():
-    """Independent patches of different sizes and orders in one batch (one
-    HIP graph per operation): block-diagonal CSR and y against the oracle
-    patch by patch."""
+@pytest.mark.parametrize("npatch,kmax,pmax,side", [(6, 6, 6, False), (6, 6, 6, True), (30, 8, 4, True)])
+def test_batched_patches(npatch, kmax, pmax, side):
+    """Independent patches of different sizes and orders in one batch:
+    persistent kernels per order with autotuned tiles; on a side stream every
+    call is one captured HIP graph, replayed.  Block-diagonal CSR and y
+    against the oracle patch by patch, on every replay."""
     import torch
-    Ks, ps = inputs.batched_draw(6, seed=2, kmin=2, kmax=6, pmin=2, pmax=6)
+    from tests.gpu_util import side_ctx
+    c, stream = side_ctx() if side else (ctx(), torch.cuda.current_stream())
+    Ks, ps = inputs.batched_draw(npatch, seed=2, kmin=2, kmax=kmax, pmin=2, pmax=pmax)
     patches, probs, xs = [], [], []
-    for b in range(6):
-        kn, ctrl, x = inputs.batched_patch(b, Ks[b], ps[b])
-        g = GpuPatch(kn, int(ps[b]), ctrl)
-        g.prepare()
-        patches.append(g)
-        probs.append(oracle.Problem(kn, int(ps[b]), ctrl))
-        xs.append(x)
-    try:
-        bt = sf.sf_batch_create(ctx(), [g.h for g in patches])
-        ro, zo = sf.sf_batch_offsets(ctx(), bt, 6)
-        Ntot, Z = int(ro[-1]), int(zo[-1])
-        rp = torch.empty(Ntot + 1, dtype=torch.int64, device="cuda")
-        ci = torch.empty(Z, dtype=torch.int32, device="cuda")
-        vm = torch.empty(Z, dtype=torch.float64, device="cuda")
-        vs = torch.empty(Z, dtype=torch.float64, device="cuda")
-        for rep in range(3):             # the cached graph is replayed; every replay must match
-            vm.fill_(float("nan"))
-            vs.fill_(float("nan"))
-            sf.sf_batch_assemble(ctx(), bt, sf.SF_MASS | sf.SF_STIFF, sf.SF_FP64, rp, ci, vm, vs)
-            torch.cuda.synchronize()
-            rpn, cin, vmn, vsn = rp.cpu().numpy(), ci.cpu().numpy(), vm.cpu().numpy(), vs.cpu().numpy()
+    with torch.cuda.stream(stream):
+        for b in range(npatch):
+            kn, ctrl, x = inputs.batched_patch(b, Ks[b], ps[b])
+            g = GpuPatch(kn, int(ps[b]), ctrl, context=c)
+            g.prepare()
+            patches.append(g)
+            probs.append(oracle.Problem(kn, int(ps[b]), ctrl))
+            xs.append(x)
+        ref = []
+        for b, P in enumerate(probs):
+            rp_o, ci_o = P.pattern()
+            vals = {op: P.assemble(op, pattern=(rp_o, ci_o))[2] for op in (sf.SF_MASS, sf.SF_STIFF)}
+            A = oracle.csr_to_dense(rp_o, ci_o, vals[sf.SF_STIFF], P.N)
+            ref.append((rp_o, ci_o, vals, A @ xs[b], np.abs(A) @ np.abs(xs[b])))
+        try:
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            ro, zo = sf.sf_batch_offsets(c, bt, npatch)
+            Ntot, Z = int(ro[-1]), int(zo[-1])
+            rp = torch.empty(Ntot + 1, dtype=torch.int64, device="cuda")
+            ci = torch.empty(Z, dtype=torch.int32, device="cuda")
+            vm = torch.empty(Z, dtype=torch.float64, device="cuda")
+            vs = torch.empty(Z, dtype=torch.float64, device="cuda")
             xall = torch.as_tensor(np.concatenate(xs)).cuda()
-            y = torch.full((Ntot,), float("nan"), dtype=torch.float64, device="cuda")
-            sf.sf_batch_apply(ctx(), bt, sf.SF_STIFF, sf.SF_FP64, xall, y)
-            torch.cuda.synchronize()
-            yn = y.cpu().numpy()
-            for b, P in enumerate(probs):
-                r0, r1, z0 = ro[b], ro[b + 1], zo[b]
-                rp_o, ci_o = P.pattern()
-                assert np.array_equal(rpn[r0:r1 + 1] - z0, rp_o)
-                assert np.array_equal(cin[z0:zo[b + 1]].astype(np.int64) - r0, ci_o)
-                for op, vals in ((sf.SF_MASS, vmn), (sf.SF_STIFF, vsn)):
-                    _, _, v_o = P.assemble(op, pattern=(rp_o, ci_o))
-                    assert err_A(vals[z0:zo[b + 1]], v_o) <= TOL64
-                A = oracle.csr_to_dense(rp_o, ci_o, P.assemble(sf.SF_STIFF, pattern=(rp_o, ci_o))[2], P.N)
-                assert err_y(yn[r0:r1], A @ xs[b], np.abs(A) @ np.abs(xs[b])) <= TOL64
-        sf.sf_batch_destroy(bt)
-    finally:
-        for g in patches:
-            g.close()
+            y = torch.empty(Ntot, dtype=torch.float64, device="cuda")
+            for rep in range(3):             # first call tunes and captures; then replays
+                vm.fill_(float("nan"))
+                vs.fill_(float("nan"))
+                y.fill_(float("nan"))
+                sf.sf_batch_assemble(c, bt, sf.SF_MASS | sf.SF_STIFF, sf.SF_FP64, rp, ci, vm, vs)
+                sf.sf_batch_apply(c, bt, sf.SF_STIFF, sf.SF_FP64, xall, y)
+                stream.synchronize()
+                rpn, cin, vmn, vsn, yn = (t.cpu().numpy() for t in (rp, ci, vm, vs, y))
+                for b in range(npatch):
+                    rp_o, ci_o, vals, y_o, absAx = ref[b]
+                    r0, r1, z0, z1 = ro[b], ro[b + 1], zo[b], zo[b + 1]
+                    assert np.array_equal(rpn[r0:r1 + 1] - z0, rp_o), (rep, b)
+                    assert np.array_equal(cin[z0:z1].astype(np.int64) - r0, ci_o), (rep, b)
+                    assert err_A(vmn[z0:z1], vals[sf.SF_MASS]) <= TOL64, (rep, b)
+                    assert err_A(vsn[z0:z1], vals[sf.SF_STIFF]) <= TOL64, (rep, b)
+                    assert err_y(yn[r0:r1], y_o, absAx) <= TOL64, (rep, b)
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
 
 
 def test_error_paths():
