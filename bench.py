@@ -90,9 +90,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--workload", choices=["single", "large", "sweep", "batched"], default="single",
+                    help="single: d=3 48^3 order 4 (the headline line); large: 128^3 order 6 with 100 applies per "
+                         "step; sweep: matrix-free apply at N = 126^3 for orders 2..9; batched: 512 patches")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--elements", type=int, default=48)
     ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--applies", type=int, default=1, help="matrix-free applies per step")
     ap.add_argument("--cpu-sample-elements", type=int, default=48,
                     help="elements per direction of the patch the oracle assembles for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,7 +118,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    prec = sf.SF_FP64 if args.prec == "fp64" else sf.SF_FP32
+    if args.workload == "sweep":
+        return run_sweep(args)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "large":
+        args.elements, args.order = 128, 6
+        args.applies = max(args.applies, 100)
+        args.prec = args.prec or "fp32"
+        args.no_cpu_baseline = True
+    prec = sf.SF_FP64 if (args.prec or "fp64") == "fp64" else sf.SF_FP32
     K = (args.elements,) * 3
     p = args.order
     w = inputs.workload_3d(K, p)
@@ -143,7 +156,8 @@ def main():
         sf.sf_assemble(ctx, h, sf.SF_STIFF, prec, val_stiff=vals)
         if ev:
             ev[3].record(stream)
-        sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
+        for _ in range(args.applies):
+            sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
         if ev:
             ev[4].record(stream)
 
@@ -167,6 +181,7 @@ def main():
     ms_per_step = (t1 - t0) / args.steps * 1e3
     stage_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(axis=0)
     geom_ms, pat_ms, asm_ms, app_ms = stage_ms.tolist()
+    app_ms /= args.applies
 
     fl_asm = assembly_flops(K, p, "stiff")
     fl_app = apply_flops(K, p, "stiff")
@@ -196,9 +211,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == sf.SF_FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_assembly_plus_apply",
+        "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_assembly_plus_"
+                               f"{args.applies}_apply",
                    "d": 3, "elements": list(K), "order": p, "ndof": N, "nnz": nnz, "nquad": Q,
-                   "coefficient": "1+0.5*sin(2pi x1)sin(2pi x2)sin(2pi x3)", "precision": args.prec},
+                   "coefficient": "1+0.5*sin(2pi x1)sin(2pi x2)sin(2pi x3)",
+                   "precision": "fp64" if prec == sf.SF_FP64 else "fp32", "applies_per_step": args.applies},
         "stages_ms": {"geometry": geom_ms, "pattern": pat_ms, "assembly": asm_ms, "apply": app_ms,
                       "tables_host_once": t_tab * 1e3},
         "assembly_gnnz_s": nnz / (asm_ms * 1e-3) / 1e9,
@@ -213,6 +230,117 @@ def main():
     sf.sf_patch_destroy(h)
     sf.sf_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+def _prec_list(args, sf):
+    return [sf.SF_FP64, sf.SF_FP32] if args.prec is None else [sf.SF_FP64 if args.prec == "fp64" else sf.SF_FP32]
+
+
+def run_sweep(args):
+    """Matrix-free stiffness apply, d = 3, K = 127 - p per direction (N = 126^3),
+    orders 2..9, one JSON line per (order, precision)."""
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    stream = torch.cuda.current_stream()
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    for p in range(2, 10):
+        w = inputs.workload_order_sweep(p)
+        K = w["K"]
+        h = sf.sf_patch_create(ctx, 3, p, w["knots"], w["ctrl"])
+        N, nnz, Q = sf.sf_patch_info(h)
+        sf.sf_patch_set_coef(ctx, h, sf.SF_STIFF, sf.SF_COEF_SINPROD, 0.5)
+        x = torch.as_tensor(w["x"]).cuda()
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        for prec in _prec_list(args, sf):
+            sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, prec)
+            for _ in range(args.warmup):
+                sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            esz = 8 if prec == sf.SF_FP64 else 4
+            byts = 6 * Q * esz + 16 * N
+            print(json.dumps({
+                "metric": "matrix-free apply GDoF/s", "value": N / (ms * 1e-3) / 1e9, "unit": "GDoF/s",
+                "ms": ms, "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+                "config": {"workload": f"d3_{K[0]}^3_p{p}_stiffness_apply", "order": p, "ndof": N, "nquad": Q},
+                "roofline": {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                             "algorithmic_bytes": byts, "algorithmic_flops": apply_flops(K, p, "stiff")}}),
+                flush=True)
+        sf.sf_patch_destroy(h)
+        del x, y
+        torch.cuda.empty_cache()
+    sf.sf_ctx_destroy(ctx)
+
+
+def run_batched(args):
+    """512 independent patches (K ~ U{4..32} per direction, p ~ U{2..6}),
+    mass and stiffness CSR assembly plus one stiffness apply per step, all
+    in captured persistent launches."""
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    prec = sf.SF_FP32 if (args.prec or "fp32") == "fp32" else sf.SF_FP64
+    stream = torch.cuda.Stream()            # captured graphs need a non-default stream
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    Ks, ps = inputs.batched_draw(512, seed=2)
+    hs = []
+    with torch.cuda.stream(stream):
+        for b in range(512):
+            kn, ctrl, _ = inputs.batched_patch(b, Ks[b], ps[b])
+            h = sf.sf_patch_create(ctx, 3, int(ps[b]), kn, ctrl)
+            sf.sf_patch_prepare(ctx, h, sf.SF_MASS | sf.SF_STIFF, prec)
+            hs.append(h)
+        bt = sf.sf_batch_create(ctx, hs)
+        ro, zo = sf.sf_batch_offsets(ctx, bt, 512)
+        N, Z = int(ro[-1]), int(zo[-1])
+        rp = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(Z, dtype=torch.int32, device="cuda")
+        vm = torch.empty(Z, dtype=torch.float64, device="cuda")
+        vs = torch.empty(Z, dtype=torch.float64, device="cuda")
+        x = torch.as_tensor(np.concatenate([inputs.batched_patch(b, Ks[b], ps[b])[2] for b in range(512)])).cuda()
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        sf.sf_batch_assemble(ctx, bt, sf.SF_MASS | sf.SF_STIFF, prec, rp, ci, vm, vs)
+        sf.sf_batch_apply(ctx, bt, sf.SF_STIFF, prec, x, y)
+        stream.synchronize()
+        t_tune = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            sf.sf_batch_assemble(ctx, bt, sf.SF_MASS | sf.SF_STIFF, prec, rp, ci, vm, vs)
+            sf.sf_batch_apply(ctx, bt, sf.SF_STIFF, prec, x, y)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            sf.sf_batch_assemble(ctx, bt, sf.SF_MASS | sf.SF_STIFF, prec, rp, ci, vm, vs)
+            ev[k][1].record(stream)
+            sf.sf_batch_apply(ctx, bt, sf.SF_STIFF, prec, x, y)
+            ev[k][2].record(stream)
+        stream.synchronize()
+        ms_step = (time.perf_counter() - t0) / args.steps * 1e3
+    asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    app_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    print(json.dumps({
+        "metric": "assembly Gnnz/s (mass + stiffness) and apply GDoF/s, batched", "value": 2 * Z / (ms_step * 1e-3) / 1e9,
+        "unit": "Gnnz/s", "ms_per_step": ms_step, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+        "config": {"workload": "batched_512_patches_K4-32_p2-6_mass_stiffness_plus_apply", "npatch": 512,
+                   "ndof": N, "nnz_per_operator": Z},
+        "stages_ms": {"assembly_mass_stiffness": asm_ms, "apply": app_ms, "first_call_tune_capture_s": t_tune},
+        "assembly_gnnz_s": 2 * Z / (asm_ms * 1e-3) / 1e9, "apply_gdof_s": N / (app_ms * 1e-3) / 1e9}), flush=True)
+    sf.sf_batch_destroy(bt)
+    for h in hs:
+        sf.sf_patch_destroy(h)
+    sf.sf_ctx_destroy(ctx)
 
 
 def cpu_leg(args, w, h, ctx, rp, ci, vals, y, K, p, prec):

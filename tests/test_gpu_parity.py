@@ -193,6 +193,46 @@ def test_3d_48cubed_p4_pattern_and_invariants():
         assert np.abs(y1).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("prec,tol", [(sf.SF_FP64, TOL64), (sf.SF_FP32, TOL32)])
+def test_3d_128cubed_p6_sampled_rows(prec, tol):
+    """Large patch: d = 3, 128^3 elements, order 6 (N = 2,352,637, nnz =
+    2,942,649,737), perturbed geometry, a = 1 + 0.5 sin sin sin; stiffness
+    assembly (in chunks of element layers) and y = A x, compared with the
+    oracle on sampled rows; only those rows leave the device."""
+    import torch
+    w = inputs.workload_3d((128, 128, 128), 6)
+    kn, p, ctrl, coef, x = w["knots"], w["p"], w["ctrl"], w["coef"], w["x"]
+    P = oracle.Problem(kn, p, ctrl, coef)
+    rows = sample_rows(P.nfun, np.random.default_rng(11), 12, coarse=True)
+    ref = P.rows(sf.SF_STIFF, rows)
+    vmax = max(np.abs(v).max() for _, v in ref)
+    with GpuPatch(kn, p, ctrl, coef) as g:
+        assert (g.N, g.nnz) == (2352637, 2942649737)
+        g.prepare(sf.SF_STIFF, prec)
+        rp = torch.empty(g.N + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(g.nnz, dtype=torch.int32, device="cuda")
+        sf.sf_csr_pattern(ctx(), g.h, rp, ci)
+        v = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+        sf.sf_assemble(ctx(), g.h, sf.SF_STIFF, prec, val_stiff=v)
+        torch.cuda.synchronize()
+        rpn = rp.cpu().numpy()
+        assert rpn[-1] == g.nnz
+        worst = 0.0
+        for r, (c, vr) in zip(rows, ref):
+            a, b = int(rpn[r]), int(rpn[r + 1])
+            assert np.array_equal(ci[a:b].cpu().numpy().astype(np.int64), c)
+            worst = max(worst, float(np.abs(v[a:b].cpu().numpy() - vr).max()))
+        assert worst / vmax <= tol, worst / vmax
+        del v, ci
+        y = g.apply(sf.SF_STIFF, x, prec)
+        absAx = np.array([np.abs(vr) @ np.abs(x[c]) for c, vr in ref])
+        ey = float(np.abs(y[rows] - P.apply_rows(sf.SF_STIFF, x, rows)).max() / absAx.max())
+        assert ey <= tol, ey
+        # K 1 = 0 on every row (partition of unity), through the matrix-free path
+        y1 = g.apply(sf.SF_STIFF, np.ones(g.N), prec)
+        assert np.abs(y1).max() <= (1e-12 if prec == sf.SF_FP64 else 1e-5) * vmax
+
+
 @pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8, 9])
 def test_order_sweep_apply_sampled(p):
     """d = 3, K = 127 - p per direction (N = 126^3 for every order), matrix-free
