@@ -166,11 +166,14 @@ sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col
  * dev_val_stiff, device [nnz] FP64 (the pointer of an operator not in ops
  * is ignored).  Needs a prior sf_patch_prepare of those operators at
  * `prec`.  Overwrites the outputs.  Deterministic: no atomics, fixed
- * summation order.  Asynchronous.  For d = 3 the first call allocates the
- * patch's level-2 workspace (the partial sums after Algorithm 1's second
- * level; at most SFIGA_WORKSPACE_MB MiB, default 4096, larger patches run
- * in chunks of element layers); it is freed by sf_patch_destroy.  Returns
- * SF_ENOMEM if that allocation fails. */
+ * summation order; the tile shapes do not change the values.
+ * Asynchronous, except that for d = 3 the first call per (operator,
+ * precision) times a few tile shapes on this patch (writing into the output,
+ * then overwriting it) and synchronizes once.  For d = 3 the first call also
+ * allocates the patch's level-2 workspace (the partial sums after the second
+ * level of Algorithm 1; at most SFIGA_WORKSPACE_MB MiB, default 4096; larger
+ * patches run in chunks of element layers); it is freed by
+ * sf_patch_destroy.  Returns SF_ENOMEM if that allocation fails. */
 sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
                       double *dev_val_mass, double *dev_val_stiff);
 

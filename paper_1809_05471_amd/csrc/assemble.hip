@@ -120,6 +120,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     using S = A12Shape<P, STIFF>;
     constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
     constexpr int WW = W * W;
+    constexpr int NP1 = STIFF ? 8 : 1;                  // pairs formed at level 1
+    // x2 points per level-1 lane (a divisor of p, bounded by registers)
+    constexpr int G2B = (P == 2 || P == 6 || P == 8) ? 2 : 1;
+    constexpr int NGB = P / G2B;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *cs = reinterpret_cast<CT *>(smem_raw);          // [NCOMP][g2][g1][XE]
     CT *l1 = cs + S::NSLICE;                            // [g2][pair][T1][W]
@@ -207,32 +211,49 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     __syncthreads();
 
     for (int e2 = 0; e2 < K2; ++e2) {
-        // ---------------- level 1: contract x1 for every row of the tile
-        for (int it = tid; it < NP * P * nrow1; it += NT) {
+        // ---------------- level 1: contract x1 for every row of the tile.
+        // One lane per (pair, row m1) forms all p x2 points of the element, so
+        // the table values of each (element, x1 point) serve p x2 points.
+        // Pair (2, 1) equals (1, 2) at this level (same tables and
+        // coefficient component) and is not formed.
+        for (int it = tid; it < NP1 * NGB * nrow1; it += NT) {
             const int lm1 = it % nrow1, rest = it / nrow1;
-            const int g2 = rest % P, pair = rest / P;
+            const int gb = rest % NGB, pi = rest / NGB;
+            const int pair = STIFF ? (pi < 7 ? pi : 8) : 0;
             const int i = STIFF ? pair / 3 : 1, j = STIFF ? pair % 3 : 1;
             const int comp = STIFF ? comp3(i, j) : 0;
             const double *ta = i == 0 ? t1D : t1B;
             const double *tb = j == 0 ? t1D : t1B;
+            const CT *cg = cs + (comp * P + gb * G2B) * P * XE;
             const int m1 = b1 + lm1;
-            CT a[W];
+            CT a[G2B][W];
 #pragma unroll
-            for (int c = 0; c < W; ++c) a[c] = CT(0);
+            for (int g = 0; g < G2B; ++g)
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[g][c] = CT(0);
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 const int e1 = m1 - r;
                 if (e1 < 0 || e1 >= K1) continue;
                 const int le1 = lm1 + P - 1 - r;
-#pragma unroll 2
+#pragma unroll 1
                 for (int g1 = 0; g1 < P; ++g1) {
-                    const CT cv = cs[((comp * P + g2) * P + g1) * XE + le1] * (CT)ta[(g1 * P + r) * XE + le1];
+                    const CT av = (CT)ta[(g1 * P + r) * XE + le1];
+                    CT bv[P];
 #pragma unroll
-                    for (int s = 0; s < P; ++s) a[s - r + P - 1] += cv * (CT)tb[(g1 * P + s) * XE + le1];
+                    for (int s = 0; s < P; ++s) bv[s] = (CT)tb[(g1 * P + s) * XE + le1];
+#pragma unroll
+                    for (int g = 0; g < G2B; ++g) {
+                        const CT cv = cg[(g * P + g1) * XE + le1] * av;
+#pragma unroll
+                        for (int s = 0; s < P; ++s) a[g][s - r + P - 1] += cv * bv[s];
+                    }
                 }
             }
 #pragma unroll
-            for (int c = 0; c < W; ++c) l1[((g2 * NP + pair) * T1 + lm1) * W + c] = a[c];
+            for (int g = 0; g < G2B; ++g)
+#pragma unroll
+                for (int c = 0; c < W; ++c) l1[(((gb * G2B + g) * NP + pair) * T1 + lm1) * W + c] = a[g][c];
         }
         __syncthreads();
         const bool more = e2 + 1 < K2;
@@ -264,7 +285,8 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                         const int pair = STIFF ? group_pair(g, kok ? k / P : 0) : 0;
                         const int g2 = k % P;
                         const int pi = STIFF ? pair / 3 : 0, pj = STIFF ? pair % 3 : 0;
-                        const double b = (kok && colok) ? (double)l1[(g2 * NP + pair) * (T1 * W) + col] : 0.0;
+                        const int lp = pair == 7 ? 5 : pair;          // (2, 1) is stored as (1, 2)
+                        const double b = (kok && colok) ? (double)l1[(g2 * NP + lp) * (T1 * W) + col] : 0.0;
                         const double *ta = pi == 1 ? t2D : t2B, *tb = pj == 1 ? t2D : t2B;
 #pragma unroll
                         for (int rb = 0; rb < S::MB; ++rb) {
@@ -306,7 +328,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 for (int g2 = 0; g2 < P; ++g2) {
                     CT L[NP];
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) L[a] = l1[((g2 * NP + a) * T1 + lm1) * W + c1];
+                    for (int a = 0; a < NP; ++a) L[a] = l1[((g2 * NP + (a == 7 ? 5 : a)) * T1 + lm1) * W + c1];
 #pragma unroll
                     for (int r = 0; r < P; ++r) {
                         const int s = r + c2 - (P - 1);
@@ -626,7 +648,7 @@ static hipError_t set_asm12_lds(const void *fn)
 
 template <int P, bool STIFF, typename CT>
 static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, void *ws, size_t ws_bytes,
-                               hipStream_t s)
+                               hipStream_t s, int t1, int seg)
 {
     using S = A12Shape<P, STIFF>;
     const size_t lds = a12_lds_bytes<P, STIFF, CT>();
@@ -642,8 +664,8 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
     if (chunk == 0 || !ws) return hipErrorInvalidValue;
     const int N3 = pv.dir[2].N, K3 = pv.dir[2].K;
     int ntile, nplane, T1r, gx3, gy3, nseg, L;
-    asm12_blocks(pv, 0, ntile, nplane, T1r);
-    asm3_blocks(pv, 0, gx3, gy3, nseg, L);
+    asm12_blocks(pv, t1, ntile, nplane, T1r);
+    asm3_blocks(pv, seg, gx3, gy3, nseg, L);
     CT *A2 = static_cast<CT *>(ws);
     for (int s0 = 0; s0 < K3; s0 += chunk) {
         const int s1 = s0 + chunk < K3 ? s0 + chunk : K3;
@@ -767,35 +789,35 @@ static hipError_t launch_asm_small(const PatchView &pv, const CT *C, double *val
 
 template <int P, typename CT>
 static hipError_t launch_asm_pt(const PatchView &pv, int op, const void *C, double *vals, void *ws,
-                                size_t ws_bytes, hipStream_t s)
+                                size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
     const CT *c = static_cast<const CT *>(C);
     if (pv.d == 3)
-        return op == 2 ? launch_asm3d<P, true, CT>(pv, c, vals, ws, ws_bytes, s)
-                       : launch_asm3d<P, false, CT>(pv, c, vals, ws, ws_bytes, s);
+        return op == 2 ? launch_asm3d<P, true, CT>(pv, c, vals, ws, ws_bytes, s, t1, seg)
+                       : launch_asm3d<P, false, CT>(pv, c, vals, ws, ws_bytes, s, t1, seg);
     return op == 2 ? launch_asm_small<P, true, CT>(pv, c, vals, s) : launch_asm_small<P, false, CT>(pv, c, vals, s);
 }
 
 template <int P>
 static hipError_t launch_asm_p(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
-                               size_t ws_bytes, hipStream_t s)
+                               size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
-    return prec == Prec::F64 ? launch_asm_pt<P, double>(pv, op, C, vals, ws, ws_bytes, s)
-                             : launch_asm_pt<P, float>(pv, op, C, vals, ws, ws_bytes, s);
+    return prec == Prec::F64 ? launch_asm_pt<P, double>(pv, op, C, vals, ws, ws_bytes, s, t1, seg)
+                             : launch_asm_pt<P, float>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
 }
 
 hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
-                           size_t ws_bytes, hipStream_t s)
+                           size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
     switch (pv.P) {
-    case 2: return launch_asm_p<2>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 3: return launch_asm_p<3>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 4: return launch_asm_p<4>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 5: return launch_asm_p<5>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 6: return launch_asm_p<6>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 7: return launch_asm_p<7>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 8: return launch_asm_p<8>(pv, op, prec, C, vals, ws, ws_bytes, s);
-    case 9: return launch_asm_p<9>(pv, op, prec, C, vals, ws, ws_bytes, s);
+    case 2: return launch_asm_p<2>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 3: return launch_asm_p<3>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 4: return launch_asm_p<4>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 5: return launch_asm_p<5>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 6: return launch_asm_p<6>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 7: return launch_asm_p<7>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 8: return launch_asm_p<8>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
+    case 9: return launch_asm_p<9>(pv, op, prec, C, vals, ws, ws_bytes, s, t1, seg);
     default: return hipErrorInvalidValue;
     }
 }

@@ -93,8 +93,10 @@ hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, c
                         hipStream_t s);
 // ws: device workspace of ws_bytes for the d = 3 level-2 partials (see
 // assemble_workspace_bytes; unused for d <= 2)
+// t1 (rows m1 per level-1/2 tile) and seg (rows m3 per level-3 segment)
+// are tile parameters (0 = default); they do not change the values.
 hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c, double *vals, void *ws,
-                           size_t ws_bytes, hipStream_t s);
+                           size_t ws_bytes, hipStream_t s, int t1 = 0, int seg = 0);
 // workspace of the d = 3 assembly of op at prec: whole patch if it fits in
 // cap bytes, else chunks of element layers (never fewer than p - 1)
 size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t cap);

@@ -39,6 +39,8 @@ struct sf_patch {
     // (operator, precision) so that captured graphs never see it move
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // autotuned assembly tile parameters per [op][prec] (-1: not yet tuned)
+    int tune_t1[2][2] = {{-1, -1}, {-1, -1}}, tune_seg[2][2] = {{-1, -1}, {-1, -1}};
     PatchView view{};
 };
 
@@ -388,13 +390,64 @@ static sf_status ensure_workspace(sf_patch *p)
     return SF_OK;
 }
 
+// Autotuner of the single-patch d = 3 assembly: rows m1 per level-1/2 tile
+// (which sets the workgroup count against the resident slots of the chip)
+// and rows m3 per level-3 segment, timed with HIP events on this patch
+// into its own output buffer (rewritten by the call that follows).  Runs
+// once per (operator, precision) and synchronizes the stream.
+static sf_status tune_assembly(sf_patch *p, int oi, int pi, double *dst)
+{
+    if (p->d != 3) {
+        p->tune_t1[oi][pi] = p->tune_seg[oi][pi] = 0;
+        return SF_OK;
+    }
+    hipStream_t s = p->ctx->stream;
+    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
+    const int tmax = asm12_max_rows(p->P);
+    std::vector<int> t1s;
+    for (int t : {tmax, (3 * tmax + 3) / 4, (tmax + 1) / 2, (tmax + 2) / 3})
+        if (t >= 1 && std::find(t1s.begin(), t1s.end(), t) == t1s.end()) t1s.push_back(t);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto run = [&](int t1, int seg) {
+        return launch_assemble(p->view, oi + 1, prec, p->C[oi][pi], dst, p->ws, p->ws_bytes, s, t1, seg);
+    };
+    auto timed = [&](int t1, int seg, float &ms) {
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = run(t1, seg);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    };
+    if (e == hipSuccess) e = run(0, 0);          // warm-up (first launch of the kernels)
+    float best = 1e30f, ms = 0.f;
+    int bt1 = 0, bseg = 0;
+    for (int t1 : t1s) {
+        timed(t1, 0, ms);
+        if (e == hipSuccess && ms < best) { best = ms; bt1 = t1; }
+    }
+    for (int seg : {8, 32}) {                    // 16 is the default just timed
+        timed(bt1, seg, ms);
+        if (e == hipSuccess && ms < best) { best = ms; bseg = seg; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly autotuning");
+    p->tune_t1[oi][pi] = bt1;
+    p->tune_seg[oi][pi] = bseg;
+    return SF_OK;
+}
+
 static sf_status assemble_into(sf_patch *p, unsigned ops, int pi, double *vm, double *vs, hipStream_t s)
 {
     for (int oi = 0; oi < 2; ++oi) {
         if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
         double *dst = oi == 0 ? vm : vs;
+        const int t1 = p->tune_t1[oi][pi] > 0 ? p->tune_t1[oi][pi] : 0;
+        const int seg = p->tune_seg[oi][pi] > 0 ? p->tune_seg[oi][pi] : 0;
         hipError_t e = launch_assemble(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], dst, p->ws,
-                                       p->ws_bytes, s);
+                                       p->ws_bytes, s, t1, seg);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly kernel");
     }
     return SF_OK;
@@ -410,6 +463,11 @@ sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, 
     if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(p->ctx, SF_EINVAL, "null output");
     st = ensure_workspace(p);
     if (st != SF_OK) return st;
+    for (int oi = 0; oi < 2; ++oi)
+        if ((ops & (oi == 0 ? SF_MASS : SF_STIFF)) && p->tune_t1[oi][pi] < 0) {
+            st = tune_assembly(p, oi, pi, oi == 0 ? vm : vs);
+            if (st != SF_OK) return st;
+        }
     return assemble_into(p, ops, pi, vm, vs, p->ctx->stream);
 }
 
@@ -592,7 +650,8 @@ static sf_status tune(sf_batch *b, int kernel, int P, int oi, int pi, const Batc
     std::vector<int> params, mults = {1, 2};
     if (kernel == KASM12) {
         const int tmax = asm12_max_rows(P);
-        params = {tmax, (tmax + 1) / 2};
+        for (int t : {tmax, (3 * tmax + 3) / 4, (tmax + 1) / 2, (tmax + 2) / 3})
+            if (t >= 1 && std::find(params.begin(), params.end(), t) == params.end()) params.push_back(t);
     } else if (kernel == KASM3) {
         params = {8, 16, 32};
         mults = {1, 2, 4};
