@@ -181,7 +181,9 @@ sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
  * Algorithm 2 backward) for one operator op; dev_x, dev_y device [N] FP64,
  * y overwritten, x and y must not overlap.  Needs a prior sf_patch_prepare
  * of op at `prec`.  Accumulates through FP64 atomics, so the last bits may
- * vary between runs.  Asynchronous. */
+ * vary between runs.  Asynchronous, except that for d = 3 the first call per
+ * (operator, precision) times a few workgroup shapes on this patch (writing
+ * into dev_y, then overwriting it) and synchronizes once. */
 sf_status sf_apply(sf_patch *patch, unsigned op, sf_precision prec, const double *dev_x, double *dev_y);
 
 /* Release the patch and its device workspace (synchronises its stream). */

@@ -62,10 +62,12 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     const int Q0 = d0.Q, Q1 = d1.Q;
     const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
 
-    // coefficients of one layer for this column: for small p all planes are
-    // held in registers and the next layer's are fetched during this one;
-    // for larger p they are read plane by plane in the pointwise stage
-    constexpr bool PRE = P * NC <= 24;
+    // coefficients of one layer for this column: when they are few (order 2
+    // stiffness, mass) all planes are held in registers and the next layer's
+    // are fetched during this one; otherwise they are read plane by plane in
+    // the pointwise stage, which keeps the registers low enough for more
+    // resident waves (measured faster from order 3 on)
+    constexpr bool PRE = P * NC <= 12;
     constexpr int NCR = PRE ? P : 1;
     CT cur[NCR][NC], nxt[NCR][NC];
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
@@ -393,7 +395,7 @@ void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &L
 }
 
 template <int P, bool STIFF, typename CT>
-static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double *x, double *y, hipStream_t s)
+static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double *x, double *y, hipStream_t s, int lz)
 {
     if (pv.d == 3) {
         const size_t lds = apply3d_lds<P, STIFF, CT>();
@@ -405,7 +407,7 @@ static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double 
             lds_set = true;
         }
         int gx, gy, gz, LZ;
-        apply_blocks(pv, 0, gx, gy, gz, LZ);
+        apply_blocks(pv, lz, gx, gy, gz, LZ);
         hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, x, y,
                            LZ);
     } else {
@@ -462,30 +464,30 @@ hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int 
 
 template <int P>
 static hipError_t launch_apply_p(const PatchView &pv, int op, Prec prec, const void *C, const double *x, double *y,
-                                 hipStream_t s)
+                                 hipStream_t s, int lz)
 {
     if (prec == Prec::F64) {
-        if (op == 2) return launch_apply_t<P, true, double>(pv, (const double *)C, x, y, s);
-        return launch_apply_t<P, false, double>(pv, (const double *)C, x, y, s);
+        if (op == 2) return launch_apply_t<P, true, double>(pv, (const double *)C, x, y, s, lz);
+        return launch_apply_t<P, false, double>(pv, (const double *)C, x, y, s, lz);
     }
-    if (op == 2) return launch_apply_t<P, true, float>(pv, (const float *)C, x, y, s);
-    return launch_apply_t<P, false, float>(pv, (const float *)C, x, y, s);
+    if (op == 2) return launch_apply_t<P, true, float>(pv, (const float *)C, x, y, s, lz);
+    return launch_apply_t<P, false, float>(pv, (const float *)C, x, y, s, lz);
 }
 
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *C, const double *x, double *y,
-                        hipStream_t s)
+                        hipStream_t s, int lz)
 {
     hipError_t e = launch_fill(y, pv.N, 0.0, s);
     if (e != hipSuccess) return e;
     switch (pv.P) {
-    case 2: return launch_apply_p<2>(pv, op, prec, C, x, y, s);
-    case 3: return launch_apply_p<3>(pv, op, prec, C, x, y, s);
-    case 4: return launch_apply_p<4>(pv, op, prec, C, x, y, s);
-    case 5: return launch_apply_p<5>(pv, op, prec, C, x, y, s);
-    case 6: return launch_apply_p<6>(pv, op, prec, C, x, y, s);
-    case 7: return launch_apply_p<7>(pv, op, prec, C, x, y, s);
-    case 8: return launch_apply_p<8>(pv, op, prec, C, x, y, s);
-    case 9: return launch_apply_p<9>(pv, op, prec, C, x, y, s);
+    case 2: return launch_apply_p<2>(pv, op, prec, C, x, y, s, lz);
+    case 3: return launch_apply_p<3>(pv, op, prec, C, x, y, s, lz);
+    case 4: return launch_apply_p<4>(pv, op, prec, C, x, y, s, lz);
+    case 5: return launch_apply_p<5>(pv, op, prec, C, x, y, s, lz);
+    case 6: return launch_apply_p<6>(pv, op, prec, C, x, y, s, lz);
+    case 7: return launch_apply_p<7>(pv, op, prec, C, x, y, s, lz);
+    case 8: return launch_apply_p<8>(pv, op, prec, C, x, y, s, lz);
+    case 9: return launch_apply_p<9>(pv, op, prec, C, x, y, s, lz);
     default: return hipErrorInvalidValue;
     }
 }

@@ -89,8 +89,9 @@ hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_in
                           int64_t col_base, int64_t nnz_base, hipStream_t s);
 hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
 // op: 1 mass, 2 stiffness; c: coefficient tensor of that op at prec
+// lz: element layers per workgroup in direction 3 (0 = default)
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, const double *x, double *y,
-                        hipStream_t s);
+                        hipStream_t s, int lz = 0);
 // ws: device workspace of ws_bytes for the d = 3 level-2 partials (see
 // assemble_workspace_bytes; unused for d <= 2)
 // t1 (rows m1 per level-1/2 tile) and seg (rows m3 per level-3 segment)

@@ -41,6 +41,7 @@ struct sf_patch {
     size_t ws_bytes = 0;
     // autotuned assembly tile parameters per [op][prec] (-1: not yet tuned)
     int tune_t1[2][2] = {{-1, -1}, {-1, -1}}, tune_seg[2][2] = {{-1, -1}, {-1, -1}};
+    int tune_lz[2][2] = {{-1, -1}, {-1, -1}};   // apply: layers per workgroup
     PatchView view{};
 };
 
@@ -482,7 +483,41 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
     if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
     if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
     int oi = op == SF_MASS ? 0 : 1;
-    hipError_t e = launch_apply(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], x, y, p->ctx->stream);
+    const Prec pr = pi == 0 ? Prec::F64 : Prec::F32;
+    hipStream_t s = p->ctx->stream;
+    if (p->tune_lz[oi][pi] < 0) {
+        // autotuner: element layers per workgroup, timed on this patch into y
+        // (rewritten by the launch below); once per (operator, precision)
+        p->tune_lz[oi][pi] = 0;
+        if (p->d == 3) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipError_t e = hipEventCreate(&e0);
+            if (e == hipSuccess) e = hipEventCreate(&e1);
+            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s);   // warm-up
+            float best = 1e30f;
+            for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
+                if (e != hipSuccess || lz > p->view.dir[2].K) break;
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
+                    float t = 0.f;
+                    e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s, lz);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+                    ms = t < ms ? t : ms;
+                }
+                if (e == hipSuccess && ms < best) {
+                    best = ms;
+                    p->tune_lz[oi][pi] = lz;
+                }
+            }
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
+        }
+    }
+    hipError_t e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s, p->tune_lz[oi][pi]);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
     return SF_OK;
 }
