@@ -93,7 +93,7 @@ def parse():
     ap.add_argument("--workload", choices=["single", "large", "sweep", "batched"], default="single",
                     help="single: d=3 48^3 order 4 (the headline line); large: 128^3 order 6 with 100 applies per "
                          "step; sweep: matrix-free apply at N = 126^3 for orders 2..9; batched: 512 patches")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default=None)
     ap.add_argument("--elements", type=int, default=48)
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--applies", type=int, default=1, help="matrix-free applies per step")
@@ -127,7 +127,7 @@ def main():
         args.applies = max(args.applies, 100)
         args.prec = args.prec or "fp32"
         args.no_cpu_baseline = True
-    prec = sf.SF_FP64 if (args.prec or "fp64") == "fp64" else sf.SF_FP32
+    prec = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "bf16": sf.SF_BF16_SPLIT}[args.prec or "fp64"]
     K = (args.elements,) * 3
     p = args.order
     w = inputs.workload_3d(K, p)
@@ -209,13 +209,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+        "dtype": {sf.SF_FP64: "f64", sf.SF_FP32: "f32", sf.SF_BF16_SPLIT: "bf16x3+f32"}[prec],
         "data": "synthetic",
         "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_assembly_plus_"
                                f"{args.applies}_apply",
                    "d": 3, "elements": list(K), "order": p, "ndof": N, "nnz": nnz, "nquad": Q,
                    "coefficient": "1+0.5*sin(2pi x1)sin(2pi x2)sin(2pi x3)",
-                   "precision": "fp64" if prec == sf.SF_FP64 else "fp32", "applies_per_step": args.applies},
+                   "precision": args.prec or "fp64", "applies_per_step": args.applies},
         "stages_ms": {"geometry": geom_ms, "pattern": pat_ms, "assembly": asm_ms, "apply": app_ms,
                       "tables_host_once": t_tab * 1e3},
         "assembly_gnnz_s": nnz / (asm_ms * 1e-3) / 1e9,

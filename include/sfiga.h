@@ -64,8 +64,15 @@ typedef enum {
 typedef enum {
     SF_FP64 = 0,           /* coefficient tensor and contractions in FP64 */
     SF_FP32 = 1,           /* coefficient tensor and contractions in FP32, FP64 output */
-    SF_BF16_SPLIT = 2,     /* reserved: BF16 MFMA with hi/lo split correction */
-    SF_FP16_SPLIT = 3      /* reserved: FP16 MFMA with hi/lo split correction */
+    SF_BF16_SPLIT = 2,     /* FP32 coefficient tensor and first contraction level;
+                              the second level of the d = 3 assembly on bf16 matrix
+                              cores, every operand split x = hi + lo (bf16) and the
+                              products hi*hi + hi*lo + lo*hi accumulated in FP32; the
+                              last level and the values in FP64 (measured error
+                              < 1e-4 of max |A|).  The apply and d <= 2 run FP32. */
+    SF_FP16_SPLIT = 3      /* not built (SF_EUNSUPPORTED): the second-level operands
+                              fall below the FP16 normal range, where the lo parts
+                              would be lost without per-block scaling */
 } sf_precision;
 
 /* operator bit flags */

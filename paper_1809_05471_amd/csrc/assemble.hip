@@ -63,6 +63,32 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x16_bf16: A[i][k] from element k % 4 of lane i + 16 (k / 4),
+// B[k][j] from element k % 4 of lane j + 16 (k / 4), D[4 (l / 16) + v][l % 16]
+// in element v of lane l
+__device__ __forceinline__ f4 mfma16x16x16bf16(s4 a, s4 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// bf16 with round-to-nearest-even, and the split x = hi + lo (hi, lo bf16):
+// hi + lo holds x to about 2^-17 relative
+__device__ __forceinline__ short bf16_rne(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(short h) { return __uint_as_float((unsigned)(unsigned short)h << 16); }
+__device__ __forceinline__ void bf16_split(float x, short &hi, short &lo)
+{
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_float(hi));
+}
+
 // Pairs (i, j), index 3 i + j, summed into one direction-3 group
 // g = 2 [i == 2] + [j == 2] (BB, BD, DB, DD of Sec. 3.1).
 __device__ __forceinline__ int group_pair(int g, int t)
@@ -113,7 +139,9 @@ __device__ __forceinline__ int comp3(int i, int j)
 
 // Levels 1 and 2 of plane x3 = q3base + by for the tile bx of rows m1.
 // A2 layout: [plane - q3base][g][m2][m1][c2][c1], c = n - m + p - 1.
-template <int P, bool STIFF, typename CT>
+// L2M: level 2 on the vector ALU (0), on FP64 matrix cores (1), on bf16
+// matrix cores with split operands and FP32 accumulation (2).
+template <int P, bool STIFF, typename CT, int L2M>
 __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__restrict__ C, CT *__restrict__ A2,
                                             int q3base, int T1r, int bx, int by)
 {
@@ -187,8 +215,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
         }
     };
 
-    constexpr bool MFMA = sizeof(CT) == sizeof(double);
-    // FP64: level-2 accumulators on the matrix cores
+    static_assert(L2M != 1 || sizeof(CT) == sizeof(double), "FP64 matrix cores take FP64 operands");
+    static_assert(L2M != 2 || sizeof(CT) == sizeof(float), "bf16 split takes FP32 operands");
+    constexpr bool MFMA = L2M == 1;
+    // level-2 accumulators on the matrix cores: FP64 (L2M 1) or FP32 (L2M 2)
     d4 macc[MFMA ? S::NBW : 1][NG][MFMA ? S::MB : 1];
 #pragma unroll
     for (int nb = 0; nb < (MFMA ? S::NBW : 1); ++nb)
@@ -196,10 +226,17 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int rb = 0; rb < (MFMA ? S::MB : 1); ++rb) macc[nb][g][rb] = d4{0.0, 0.0, 0.0, 0.0};
-    // FP32: level-2 entries of this thread, it = c1 + W (c2 + W lm1)
-    CT acc[MFMA ? 1 : S::ITEMS][P][NG];
+    f4 facc[L2M == 2 ? S::NBW : 1][NG][L2M == 2 ? S::MB : 1];
 #pragma unroll
-    for (int k = 0; k < (MFMA ? 1 : S::ITEMS); ++k)
+    for (int nb = 0; nb < (L2M == 2 ? S::NBW : 1); ++nb)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int rb = 0; rb < (L2M == 2 ? S::MB : 1); ++rb) facc[nb][g][rb] = f4{0.f, 0.f, 0.f, 0.f};
+    // vector ALU: level-2 entries of this thread, it = c1 + W (c2 + W lm1)
+    CT acc[L2M == 0 ? S::ITEMS : 1][P][NG];
+#pragma unroll
+    for (int k = 0; k < (L2M == 0 ? S::ITEMS : 1); ++k)
 #pragma unroll
         for (int r = 0; r < P; ++r)
 #pragma unroll
@@ -318,9 +355,80 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                         }
                     }
             }
+        } else if constexpr (L2M == 2) {
+            // as the FP64 path with K in steps of 16; every operand x = hi + lo
+            // in bf16 and A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, accumulated in FP32
+            const int ph = e2 % P;
+            const int lane = tid & 63, wave = tid >> 6;
+            const int ncols = nrow1 * W;
+#pragma unroll
+            for (int nb = 0; nb < S::NBW; ++nb) {
+                const int cb = wave + nb * S::NW;
+                if (cb * 16 >= ncols) break;
+                const int col = cb * 16 + (lane & 15);
+                const bool colok = col < ncols;
+                const int kq = lane >> 4;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int nk = (STIFF ? group_npairs(g) : 1) * P;
+#pragma unroll 1
+                    for (int ks = 0; ks < (4 * P + 15) / 16; ++ks) {
+                        if (ks * 16 >= nk) break;
+                        s4 bhi, blo, ahi[S::MB], alo[S::MB];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int k = ks * 16 + 4 * kq + e;
+                            const bool kok = k < nk;
+                            const int pair = STIFF ? group_pair(g, kok ? k / P : 0) : 0;
+                            const int g2 = k % P;
+                            const int pi = STIFF ? pair / 3 : 0, pj = STIFF ? pair % 3 : 0;
+                            const int lp = pair == 7 ? 5 : pair;      // (2, 1) is stored as (1, 2)
+                            const float b = (kok && colok) ? (float)l1[(g2 * NP + lp) * (T1 * W) + col] : 0.f;
+                            short h, l;
+                            bf16_split(b, h, l);
+                            bhi[e] = h;
+                            blo[e] = l;
+                            const double *ta = pi == 1 ? t2D : t2B, *tb = pj == 1 ? t2D : t2B;
+#pragma unroll
+                            for (int rb = 0; rb < S::MB; ++rb) {
+                                const int i = (lane & 15) + 16 * rb;
+                                const int r = (i / P - ph + P) % P, sj = (i % P - ph + P) % P;
+                                const float a = (kok && i < S::NSLOT) ? (float)(ta[g2 * P + r] * tb[g2 * P + sj]) : 0.f;
+                                bf16_split(a, h, l);
+                                ahi[rb][e] = h;
+                                alo[rb][e] = l;
+                            }
+                        }
+#pragma unroll
+                        for (int rb = 0; rb < S::MB; ++rb) {
+                            facc[nb][g][rb] = mfma16x16x16bf16(ahi[rb], bhi, facc[nb][g][rb]);
+                            facc[nb][g][rb] = mfma16x16x16bf16(ahi[rb], blo, facc[nb][g][rb]);
+                            facc[nb][g][rb] = mfma16x16x16bf16(alo[rb], bhi, facc[nb][g][rb]);
+                        }
+                    }
+                }
+                const int lm1 = col / W, c1 = col % W;
+                CT *dst = A2p + (int64_t)(b1 + lm1) * WW + c1;
+#pragma unroll
+                for (int rb = 0; rb < S::MB; ++rb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 4 * (lane >> 4) + v + 16 * rb;
+                        const int ms = i / P, ns = i % P;
+                        if (i < S::NSLOT && (last || ms == ph || ns == ph)) {
+                            const int m2 = e2 + (ms - ph + P) % P, n2 = e2 + (ns - ph + P) % P;
+                            const int c2 = n2 - m2 + P - 1;
+#pragma unroll
+                            for (int g = 0; g < NG; ++g) {
+                                if (colok) dst[((int64_t)g * N2 + m2) * rowsz + c2 * W] = (CT)facc[nb][g][rb][v];
+                                facc[nb][g][rb][v] = 0.f;
+                            }
+                        }
+                    }
+            }
         } else {
 #pragma unroll
-            for (int k = 0; k < (MFMA ? 1 : S::ITEMS); ++k) {
+            for (int k = 0; k < (L2M == 0 ? S::ITEMS : 1); ++k) {
                 const int it = tid + k * NT;
                 if (it >= nitems) continue;
                 const int c1 = it % W, c2 = (it / W) % W, lm1 = it / WW;
@@ -369,11 +477,11 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     }
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
                                                                         CT *__restrict__ A2, int q3base, int T1r)
 {
-    asm12_block<P, STIFF, CT>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
+    asm12_block<P, STIFF, CT, L2M>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
 }
 
 // Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
@@ -572,7 +680,7 @@ __global__ void asm_small_kernel(PatchView pv, const CT *__restrict__ C, double 
 static size_t a2_plane_bytes(const PatchView &pv, int op, Prec prec)
 {
     const int W = 2 * pv.P - 1, NG = op == 2 ? 4 : 1;
-    return (size_t)NG * pv.dir[1].N * pv.dir[0].N * W * W * (prec == Prec::F64 ? sizeof(double) : sizeof(float));
+    return (size_t)NG * pv.dir[1].N * pv.dir[0].N * W * W * (prec == Prec::F64 ? sizeof(double) : sizeof(float));   // BF16X3: FP32
 }
 
 // element layers per chunk for a workspace of the given size (0: too small)
@@ -646,7 +754,7 @@ static hipError_t set_asm12_lds(const void *fn)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, void *ws, size_t ws_bytes,
                                hipStream_t s, int t1, int seg)
 {
@@ -654,12 +762,12 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
     const size_t lds = a12_lds_bytes<P, STIFF, CT>();
     static bool lds_set = false;     // per instantiation: raise the dynamic LDS limit once
     if (!lds_set) {
-        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_kernel<P, STIFF, CT>);
+        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_kernel<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
         lds_set = true;
     }
     const int op = STIFF ? 2 : 1;
-    const Prec prec = sizeof(CT) == sizeof(double) ? Prec::F64 : Prec::F32;
+    const Prec prec = sizeof(CT) == sizeof(double) ? Prec::F64 : Prec::F32;   // workspace element size
     const int chunk = a2_chunk(pv, op, prec, ws_bytes);
     if (chunk == 0 || !ws) return hipErrorInvalidValue;
     const int N3 = pv.dir[2].N, K3 = pv.dir[2].K;
@@ -669,8 +777,8 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
     CT *A2 = static_cast<CT *>(ws);
     for (int s0 = 0; s0 < K3; s0 += chunk) {
         const int s1 = s0 + chunk < K3 ? s0 + chunk : K3;
-        hipLaunchKernelGGL((asm12_kernel<P, STIFF, CT>), dim3(ntile, (s1 - s0) * P), dim3(S::NT), lds, s, pv, C, A2,
-                           s0 * P, T1r);
+        hipLaunchKernelGGL((asm12_kernel<P, STIFF, CT, L2M>), dim3(ntile, (s1 - s0) * P), dim3(S::NT), lds, s, pv, C,
+                           A2, s0 * P, T1r);
         const int last_row = s1 + P - 2 < N3 - 1 ? s1 + P - 2 : N3 - 1;
         const int seg0 = s0 / L, seg1 = last_row / L;
         hipLaunchKernelGGL((asm3_kernel<P, STIFF, CT>), dim3(gx3, gy3, seg1 - seg0 + 1), dim3(256), 0, s, pv,
@@ -683,14 +791,14 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
 
 // Persistent forms: each workgroup takes blocks it = blockIdx.x, + gridDim.x,
 // ... of the concatenated per-patch grids (every patch in one chunk).
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_persistent(TaskList tl)
 {
     for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
         const int t = task_of(tl.off, tl.ntask, it);
         const BatchTask &T = tl.tasks[t];
         const int64_t l = it - tl.off[t];
-        asm12_block<P, STIFF, CT>(T.pv, (const CT *)T.C, (CT *)T.ws, 0, T.arg, (int)(l % T.gx), (int)(l / T.gx));
+        asm12_block<P, STIFF, CT, L2M>(T.pv, (const CT *)T.C, (CT *)T.ws, 0, T.arg, (int)(l % T.gx), (int)(l / T.gx));
         __syncthreads();   // LDS of the next block
     }
 }
@@ -709,18 +817,18 @@ __global__ __launch_bounds__(256) void asm3_persistent(TaskList tl)
     }
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t launch_asm12_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
 {
     static bool lds_set = false;
     if (!lds_set) {
-        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_persistent<P, STIFF, CT>);
+        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_persistent<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
         lds_set = true;
     }
     constexpr int NT = A12Shape<P, STIFF>::NT;
     const size_t lds = a12_lds_bytes<P, STIFF, CT>();
-    hipLaunchKernelGGL((asm12_persistent<P, STIFF, CT>), dim3(nblocks), dim3(NT), lds, s, tl);
+    hipLaunchKernelGGL((asm12_persistent<P, STIFF, CT, L2M>), dim3(nblocks), dim3(NT), lds, s, tl);
     return hipGetLastError();
 }
 
@@ -736,10 +844,13 @@ static hipError_t launch_batch_p(int which, const TaskList &tl, int op, Prec pre
 {
     if (which == 0) {
         if (prec == Prec::F64)
-            return op == 2 ? launch_asm12_batch_t<P, true, double>(tl, nblocks, s)
-                           : launch_asm12_batch_t<P, false, double>(tl, nblocks, s);
-        return op == 2 ? launch_asm12_batch_t<P, true, float>(tl, nblocks, s)
-                       : launch_asm12_batch_t<P, false, float>(tl, nblocks, s);
+            return op == 2 ? launch_asm12_batch_t<P, true, double, 1>(tl, nblocks, s)
+                           : launch_asm12_batch_t<P, false, double, 1>(tl, nblocks, s);
+        if (prec == Prec::BF16X3)
+            return op == 2 ? launch_asm12_batch_t<P, true, float, 2>(tl, nblocks, s)
+                           : launch_asm12_batch_t<P, false, float, 2>(tl, nblocks, s);
+        return op == 2 ? launch_asm12_batch_t<P, true, float, 0>(tl, nblocks, s)
+                       : launch_asm12_batch_t<P, false, float, 0>(tl, nblocks, s);
     }
     if (prec == Prec::F64)
         return op == 2 ? launch_asm3_batch_t<P, true, double>(tl, nblocks, s)
@@ -787,14 +898,14 @@ static hipError_t launch_asm_small(const PatchView &pv, const CT *C, double *val
     return hipGetLastError();
 }
 
-template <int P, typename CT>
+template <int P, typename CT, int L2M>
 static hipError_t launch_asm_pt(const PatchView &pv, int op, const void *C, double *vals, void *ws,
                                 size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
     const CT *c = static_cast<const CT *>(C);
     if (pv.d == 3)
-        return op == 2 ? launch_asm3d<P, true, CT>(pv, c, vals, ws, ws_bytes, s, t1, seg)
-                       : launch_asm3d<P, false, CT>(pv, c, vals, ws, ws_bytes, s, t1, seg);
+        return op == 2 ? launch_asm3d<P, true, CT, L2M>(pv, c, vals, ws, ws_bytes, s, t1, seg)
+                       : launch_asm3d<P, false, CT, L2M>(pv, c, vals, ws, ws_bytes, s, t1, seg);
     return op == 2 ? launch_asm_small<P, true, CT>(pv, c, vals, s) : launch_asm_small<P, false, CT>(pv, c, vals, s);
 }
 
@@ -802,8 +913,9 @@ template <int P>
 static hipError_t launch_asm_p(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
                                size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
-    return prec == Prec::F64 ? launch_asm_pt<P, double>(pv, op, C, vals, ws, ws_bytes, s, t1, seg)
-                             : launch_asm_pt<P, float>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
+    if (prec == Prec::F64) return launch_asm_pt<P, double, 1>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
+    if (prec == Prec::BF16X3) return launch_asm_pt<P, float, 2>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
+    return launch_asm_pt<P, float, 0>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
 }
 
 hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,

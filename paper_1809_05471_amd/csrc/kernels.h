@@ -8,7 +8,10 @@
 
 namespace sfiga {
 
-enum class Prec { F64 = 0, F32 = 1 };
+// F64, F32: every contraction in that type; BF16X3: FP32 coefficients and level 1,
+// level 2 of the assembly on bf16 matrix cores with hi/lo split operands and
+// FP32 accumulation (level 3 and the values stay FP64).
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 // Element tile of the d = 3 tile kernels in directions 1 and 2: about 32 x 16
 // quadrature points per workgroup (one thread per quadrature column).

@@ -33,15 +33,15 @@ struct sf_patch {
     double *dctrl = nullptr;
     int *dflag = nullptr;
     Coef coef[2];                 // [0] mass, [1] stiffness
-    void *C[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [op][prec]
-    bool ready[2][2] = {{false, false}, {false, false}};
+    void *C[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [op][FP64, FP32 storage]
+    bool ready[2][3] = {{false, false, false}, {false, false, false}};   // [op][precision mode]
     // level-2 workspace of the d = 3 assembly, sized once for the largest
     // (operator, precision) so that captured graphs never see it move
     void *ws = nullptr;
     size_t ws_bytes = 0;
     // autotuned assembly tile parameters per [op][prec] (-1: not yet tuned)
-    int tune_t1[2][2] = {{-1, -1}, {-1, -1}}, tune_seg[2][2] = {{-1, -1}, {-1, -1}};
-    int tune_lz[2][2] = {{-1, -1}, {-1, -1}};   // apply: layers per workgroup
+    int tune_t1[2][3] = {{-1, -1, -1}, {-1, -1, -1}}, tune_seg[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    int tune_lz[2][3] = {{-1, -1, -1}, {-1, -1, -1}};   // apply: layers per workgroup
     PatchView view{};
 };
 
@@ -93,12 +93,19 @@ hipError_t upload(T **dst, const T *src, size_t n, hipStream_t s)
     return e;
 }
 
+// Precision modes: 0 FP64, 1 FP32, 2 BF16 split (FP32 coefficients and
+// level 1, level 2 of the assembly on bf16 matrix cores with a hi/lo split).
 bool prec_index(sf_precision prec, int &pi)
 {
     if (prec == SF_FP64) { pi = 0; return true; }
     if (prec == SF_FP32) { pi = 1; return true; }
+    if (prec == SF_BF16_SPLIT) { pi = 2; return true; }
     return false;
 }
+
+int cidx(int pi) { return pi == 0 ? 0 : 1; }                      // coefficient tensor storage
+Prec asm_prec(int pi) { return pi == 0 ? Prec::F64 : (pi == 1 ? Prec::F32 : Prec::BF16X3); }
+Prec apply_prec(int pi) { return pi == 0 ? Prec::F64 : Prec::F32; }   // no dense contraction for bf16
 
 int ncomp(int op_idx, int d) { return op_idx == 0 ? 1 : d * (d + 1) / 2; }
 
@@ -283,7 +290,7 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
     }
     int oi = op == SF_MASS ? 0 : 1;
     p->coef[oi] = c;
-    p->ready[oi][0] = p->ready[oi][1] = false;
+    p->ready[oi][0] = p->ready[oi][1] = p->ready[oi][2] = false;
     return SF_OK;
 }
 
@@ -309,13 +316,15 @@ sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
     if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
     int pi;
     if (!prec_index(prec, pi)) {
-        if (prec == SF_BF16_SPLIT || prec == SF_FP16_SPLIT) return fail(ctx, SF_EUNSUPPORTED, "precision not built");
+        if (prec == SF_FP16_SPLIT)
+            return fail(ctx, SF_EUNSUPPORTED, "FP16 split not built: the level-2 operands fall below the FP16 range");
         return fail(ctx, SF_EINVAL, "bad precision");
     }
     hipStream_t s = ctx->stream;
-    const size_t esz = pi == 0 ? sizeof(double) : sizeof(float);
+    const int ci = cidx(pi);
+    const size_t esz = ci == 0 ? sizeof(double) : sizeof(float);
     GeomOut o{};
-    o.prec = pi == 0 ? Prec::F64 : Prec::F32;
+    o.prec = ci == 0 ? Prec::F64 : Prec::F32;
     o.bad_det = p->dflag;
     o.coef_mass = p->coef[0];
     o.coef_stiff = p->coef[1];
@@ -323,15 +332,16 @@ sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
         unsigned bit = oi == 0 ? SF_MASS : SF_STIFF;
         if (!(ops & bit)) continue;
         if (p->coef[oi].kind == 2 && !p->coef[oi].qp) return fail(ctx, SF_EINVAL, "missing quadrature values");
-        if (!p->C[oi][pi]) {
-            hipError_t e = hipMalloc(&p->C[oi][pi], esz * (size_t)p->view.Q * ncomp(oi, p->d));
+        if (!p->C[oi][ci]) {
+            hipError_t e = hipMalloc(&p->C[oi][ci], esz * (size_t)p->view.Q * ncomp(oi, p->d));
             if (e != hipSuccess) {
-                p->C[oi][pi] = nullptr;
+                p->C[oi][ci] = nullptr;
                 return hip_fail(ctx, e, "coefficient tensor allocation");
             }
         }
-        p->ready[oi][pi] = false;
-        if (oi == 0) o.c_mass = p->C[oi][pi]; else o.c_stiff = p->C[oi][pi];
+        for (int m = 0; m < 3; ++m)
+            if (cidx(m) == ci) p->ready[oi][m] = false;
+        if (oi == 0) o.c_mass = p->C[oi][ci]; else o.c_stiff = p->C[oi][ci];
     }
     hipError_t e = hipMemsetAsync(p->dflag, 0, sizeof(int), s);
     if (e == hipSuccess) e = launch_geometry(p->view, o, s);
@@ -341,7 +351,9 @@ sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
     if (e != hipSuccess) return hip_fail(ctx, e, "geometry step");
     if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
     for (int oi = 0; oi < 2; ++oi)
-        if (ops & (oi == 0 ? SF_MASS : SF_STIFF)) p->ready[oi][pi] = true;
+        if (ops & (oi == 0 ? SF_MASS : SF_STIFF))
+            for (int m = 0; m < 3; ++m)
+                if (cidx(m) == ci) p->ready[oi][m] = true;     // FP32 storage serves FP32 and BF16 split
     return SF_OK;
 }
 
@@ -359,7 +371,8 @@ static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &
     sf_ctx *ctx = p->ctx;
     if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
     if (!prec_index(prec, pi)) {
-        if (prec == SF_BF16_SPLIT || prec == SF_FP16_SPLIT) return fail(ctx, SF_EUNSUPPORTED, "precision not built");
+        if (prec == SF_FP16_SPLIT)
+            return fail(ctx, SF_EUNSUPPORTED, "FP16 split not built: the level-2 operands fall below the FP16 range");
         return fail(ctx, SF_EINVAL, "bad precision");
     }
     for (int oi = 0; oi < 2; ++oi)
@@ -403,7 +416,7 @@ static sf_status tune_assembly(sf_patch *p, int oi, int pi, double *dst)
         return SF_OK;
     }
     hipStream_t s = p->ctx->stream;
-    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
+    const Prec prec = asm_prec(pi);
     const int tmax = asm12_max_rows(p->P);
     std::vector<int> t1s;
     for (int t : {tmax, (3 * tmax + 3) / 4, (tmax + 1) / 2, (tmax + 2) / 3})
@@ -412,7 +425,7 @@ static sf_status tune_assembly(sf_patch *p, int oi, int pi, double *dst)
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     auto run = [&](int t1, int seg) {
-        return launch_assemble(p->view, oi + 1, prec, p->C[oi][pi], dst, p->ws, p->ws_bytes, s, t1, seg);
+        return launch_assemble(p->view, oi + 1, prec, p->C[oi][cidx(pi)], dst, p->ws, p->ws_bytes, s, t1, seg);
     };
     auto timed = [&](int t1, int seg, float &ms) {
         if (e == hipSuccess) e = hipEventRecord(e0, s);
@@ -447,7 +460,7 @@ static sf_status assemble_into(sf_patch *p, unsigned ops, int pi, double *vm, do
         double *dst = oi == 0 ? vm : vs;
         const int t1 = p->tune_t1[oi][pi] > 0 ? p->tune_t1[oi][pi] : 0;
         const int seg = p->tune_seg[oi][pi] > 0 ? p->tune_seg[oi][pi] : 0;
-        hipError_t e = launch_assemble(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->C[oi][pi], dst, p->ws,
+        hipError_t e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, p->ws,
                                        p->ws_bytes, s, t1, seg);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly kernel");
     }
@@ -483,7 +496,8 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
     if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
     if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
     int oi = op == SF_MASS ? 0 : 1;
-    const Prec pr = pi == 0 ? Prec::F64 : Prec::F32;
+    const Prec pr = apply_prec(pi);
+    const void *C = p->C[oi][cidx(pi)];
     hipStream_t s = p->ctx->stream;
     if (p->tune_lz[oi][pi] < 0) {
         // autotuner: element layers per workgroup, timed on this patch into y
@@ -493,7 +507,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             hipEvent_t e0 = nullptr, e1 = nullptr;
             hipError_t e = hipEventCreate(&e0);
             if (e == hipSuccess) e = hipEventCreate(&e1);
-            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s);   // warm-up
+            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s);   // warm-up
             float best = 1e30f;
             for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
                 if (e != hipSuccess || lz > p->view.dir[2].K) break;
@@ -501,7 +515,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
                     float t = 0.f;
                     e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s, lz);
+                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz);
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -517,7 +531,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
         }
     }
-    hipError_t e = launch_apply(p->view, oi + 1, pr, p->C[oi][pi], x, y, s, p->tune_lz[oi][pi]);
+    hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi]);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
     return SF_OK;
 }
@@ -592,7 +606,7 @@ static bool persistent_ok(const sf_patch *p, int kernel, int oi, int pi)
     if (kernel == KROWPTR || kernel == KCOLIND) return true;
     if (p->d != 3) return false;
     if (kernel == KAPPLY) return true;
-    return assemble_single_chunk(p->view, oi + 1, pi == 0 ? Prec::F64 : Prec::F32, p->ws_bytes);
+    return assemble_single_chunk(p->view, oi + 1, asm_prec(pi), p->ws_bytes);
 }
 
 // Tasks of one kernel for the patches of order P (P = 0: all orders), largest
@@ -605,7 +619,7 @@ static HostTasks build_tasks(const sf_batch *b, int kernel, int P, int oi, int p
         if ((P && p->P != P) || !persistent_ok(p, kernel, oi, pi)) continue;
         BatchTask T{};
         T.pv = p->view;
-        T.C = p->C[oi][pi];
+        T.C = p->C[oi][cidx(pi)];
         T.ws = p->ws;
         const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
         T.gy = T.gz = 1;
@@ -660,11 +674,10 @@ static hipError_t upload_tasks(const HostTasks &h, TaskList &tl, void **mem)
 
 static hipError_t launch_kernel(int kernel, const TaskList &tl, int P, int oi, int pi, int nblocks, hipStream_t s)
 {
-    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
     switch (kernel) {
-    case KASM12: return launch_asm12_batch(tl, P, oi + 1, prec, nblocks, s);
-    case KASM3: return launch_asm3_batch(tl, P, oi + 1, prec, nblocks, s);
-    case KAPPLY: return launch_apply_batch(tl, P, oi + 1, prec, nblocks, s);
+    case KASM12: return launch_asm12_batch(tl, P, oi + 1, asm_prec(pi), nblocks, s);
+    case KASM3: return launch_asm3_batch(tl, P, oi + 1, asm_prec(pi), nblocks, s);
+    case KAPPLY: return launch_apply_batch(tl, P, oi + 1, apply_prec(pi), nblocks, s);
     case KROWPTR: return launch_rowptr_batch(tl, nblocks, s);
     default: return launch_colind_batch(tl, P, nblocks, s);
     }
@@ -793,7 +806,6 @@ static sf_status plan_call(sf_batch *b, int kind, unsigned ops, int pi, const Ba
 static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const BatchIO &io_in,
                              const std::vector<Plan> &plan, hipStream_t s)
 {
-    const Prec prec = pi == 0 ? Prec::F64 : Prec::F32;
     if (kind == 1) {
         hipError_t e = launch_fill(io_in.y, b->row_off.back(), 0.0, s);
         if (e != hipSuccess) return hip_fail(b->ctx, e, "fill");
@@ -815,9 +827,9 @@ static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const 
             hipError_t e;
             if (kind == 0) {
                 double *dst = io_in.vals[oi] + z0;
-                e = launch_assemble(p->view, oi + 1, prec, p->C[oi][pi], dst, p->ws, p->ws_bytes, s);
+                e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, p->ws, p->ws_bytes, s);
             } else {
-                e = launch_apply(p->view, oi + 1, prec, p->C[oi][pi], io_in.x + r0, io_in.y + r0, s);
+                e = launch_apply(p->view, oi + 1, apply_prec(pi), p->C[oi][cidx(pi)], io_in.x + r0, io_in.y + r0, s);
             }
             if (e != hipSuccess) return hip_fail(b->ctx, e, "per-patch kernel");
         }

@@ -18,6 +18,10 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 2e-5
+# BF16 split: operands x = hi + lo in bf16 hold x to 2^-17; a product keeps
+# Ahi Bhi + Ahi Blo + Alo Bhi (dropping Alo Blo ~ 2^-18), so each level-2
+# term carries about 2^-16 relative error before the FP32 and FP64 sums
+TOLBF = 2e-4
 
 
 def _full_parity(knots, p, ctrl, coef, ops=(sf.SF_MASS, sf.SF_STIFF), prec=sf.SF_FP64, tol=TOL64, seed=0):
@@ -70,6 +74,19 @@ def test_3d_full_parity_several_tiles(K, p):
 def test_3d_fp32_mode(K, p):
     kn, ctrl = inputs.perturbed_geometry(K, p, seed=4)
     _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP32, tol=TOL32)
+
+
+@pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((13, 4, 6), 3), ((21, 3, 5), 4), ((3, 4, 3), 5), ((2, 3, 2), 6),
+                                 ((2, 2, 2), 8)])
+def test_3d_bf16_split_mode(K, p):
+    """Level 2 of the assembly on bf16 matrix cores with hi/lo split operands
+    and FP32 accumulation (FP32 coefficients and level 1, FP64 level 3 and
+    values); the apply runs its FP32 path.  Parity unpinned by the paper:
+    checked against the FP64 oracle with the bound TOLBF."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=4)
+    res = _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_BF16_SPLIT, tol=TOLBF)
+    # the split keeps far more than bf16 alone (2^-9 ~ 2e-3) would
+    assert max(eA for eA, _ in res.values()) < 1e-4
 
 
 @pytest.mark.parametrize("K,p", [((17,), 2), ((5,), 5), ((30,), 9)])
@@ -316,6 +333,9 @@ def test_error_paths():
         with pytest.raises(sf.SfError) as e:
             g.prepare(prec=sf.SF_BF16_SPLIT + 7)
         assert e.value.status == sf.SF_EINVAL
+        with pytest.raises(sf.SfError) as e:
+            g.prepare(prec=sf.SF_FP16_SPLIT)
+        assert e.value.status == sf.SF_EUNSUPPORTED
         g.prepare()
         assert g.assemble(sf.SF_STIFF).shape == (g.nnz,)     # still usable after errors
     bad = [k.copy() for k in kn]
