@@ -60,17 +60,32 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
 
 // One workgroup per (E1 x E2 element tile, element layer e3).  Threads own a
 // quadrature column (q1, q2); the three contractions run 3 -> 2 -> 1 through
-// LDS, one quadrature plane g3 at a time.
+// LDS for NPS quadrature planes g3 at a time (all p planes of the layer for
+// p <= 4, so that each stage has several items per thread and the layer
+// needs three barriers; one plane at a time above, to bound LDS).
+template <int P> struct GeomPlanes { static constexpr int NPS = P <= 4 ? P : 1; };
+
+template <int P>
+constexpr size_t geom3d_lds()
+{
+    using TL = Tile<P>;
+    constexpr int NPS = GeomPlanes<P>::NPS;
+    return sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * NPS * TL::NY * TL::NX + 9 * NPS * TL::TY * TL::NX +
+                             2 * (TL::E1 + TL::E2) * P * P);
+}
+
 template <int P>
 __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomOut o)
 {
     using TL = Tile<P>;
     constexpr int NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY;
+    constexpr int NPS = GeomPlanes<P>::NPS;
+    constexpr int NYX = NY * NX, TYX = TY * NX;
     extern __shared__ double smem[];
     double *cw = smem;                         // [3][P][NY][NX] control points
-    double *sa = cw + 3 * P * NY * NX;         // [6][NY][NX]   B3 c, D3 c at g3
-    double *sb = sa + 6 * NY * NX;             // [9][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
-    double *t1B = sb + 9 * TY * NX, *t1D = t1B + TL::E1 * P * P;      // tile tables [elem][g][j]
+    double *sa = cw + 3 * P * NYX;             // [NPS][6][NY][NX]   B3 c, D3 c at g3
+    double *sb = sa + 6 * NPS * NYX;           // [NPS][9][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
+    double *t1B = sb + 9 * NPS * TYX, *t1D = t1B + TL::E1 * P * P;   // tile tables [elem][g][j]
     double *t2B = t1D + TL::E1 * P * P, *t2D = t2B + TL::E2 * P * P;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
@@ -78,7 +93,7 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
     const int tid = threadIdx.x;
     const bool f32 = o.prec == Prec::F32;
 
-    for (int idx = tid; idx < 3 * P * NY * NX; idx += TL::NT) {
+    for (int idx = tid; idx < 3 * P * NYX; idx += TL::NT) {
         int lx = idx % NX, r = idx / NX;
         int ly = r % NY; r /= NY;
         int s3 = r % P, c = r / P;
@@ -107,72 +122,85 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
     const int tx = tid % TX, ty = tid / TX;
     const int le1 = tx / P, g1 = tx % P, le2 = ty / P, g2 = ty % P;
     const int e1 = e1b + le1, e2 = e2b + le2;
-    const bool active = e1 < d0.K && e2 < d1.K;
+    const bool active = tid < TX * TY && e1 < d0.K && e2 < d1.K;
 
-    for (int g3 = 0; g3 < P; ++g3) {
-        const double *b3 = d2.B + ((int64_t)e3 * P + g3) * P;
-        const double *db3 = d2.D + ((int64_t)e3 * P + g3) * P;
-        for (int idx = tid; idx < NY * NX; idx += TL::NT) {
+    for (int g3b = 0; g3b < P; g3b += NPS) {
+        // direction 3: value and derivative of the control-point columns
+        for (int it = tid; it < NPS * NYX; it += TL::NT) {
+            const int gg = it / NYX, idx = it % NYX;
+            const int g3 = g3b + gg;
+            const double *b3 = d2.B + ((int64_t)e3 * P + g3) * P;
+            const double *db3 = d2.D + ((int64_t)e3 * P + g3) * P;
             for (int c = 0; c < 3; ++c) {
                 double a = 0.0, b = 0.0;
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
-                    double v = cw[(c * P + s) * NY * NX + idx];
+                    double v = cw[(c * P + s) * NYX + idx];
                     a += b3[s] * v;
                     b += db3[s] * v;
                 }
-                sa[c * NY * NX + idx] = a;
-                sa[(3 + c) * NY * NX + idx] = b;
+                sa[(gg * 6 + c) * NYX + idx] = a;
+                sa[(gg * 6 + 3 + c) * NYX + idx] = b;
             }
         }
         __syncthreads();
-        for (int idx = tid; idx < TY * NX; idx += TL::NT) {
-            int lx = idx % NX, yy = idx / NX;
-            int l2 = yy / P, h2 = yy % P, ee2 = e2b + l2;
+        // direction 2
+        for (int it = tid; it < NPS * TYX; it += TL::NT) {
+            const int gg = it / TYX, idx = it % TYX;
+            const int lx = idx % NX, yy = idx / NX;
+            const int l2 = yy / P, h2 = yy % P, ee2 = e2b + l2;
             if (ee2 >= d1.K) continue;
             const double *b2 = t2B + (l2 * P + h2) * P;
             const double *db2 = t2D + (l2 * P + h2) * P;
+            const double *sg = sa + gg * 6 * NYX;
+            double *so = sb + gg * 9 * TYX;
             for (int c = 0; c < 3; ++c) {
                 double vb = 0.0, vd = 0.0, wb = 0.0;
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
-                    double a = sa[(c * NY + l2 + s) * NX + lx];
-                    double b = sa[((3 + c) * NY + l2 + s) * NX + lx];
+                    double a = sg[(c * NY + l2 + s) * NX + lx];
+                    double b = sg[((3 + c) * NY + l2 + s) * NX + lx];
                     vb += b2[s] * a;
                     vd += db2[s] * a;
                     wb += b2[s] * b;
                 }
-                sb[((3 * c + 0) * TY + yy) * NX + lx] = vb;
-                sb[((3 * c + 1) * TY + yy) * NX + lx] = vd;
-                sb[((3 * c + 2) * TY + yy) * NX + lx] = wb;
+                so[(3 * c + 0) * TYX + idx] = vb;
+                so[(3 * c + 1) * TYX + idx] = vd;
+                so[(3 * c + 2) * TYX + idx] = wb;
             }
         }
         __syncthreads();
+        // direction 1 and the pointwise quantities
         if (active) {
             const double *b1 = t1B + (le1 * P + g1) * P;
             const double *db1 = t1D + (le1 * P + g1) * P;
-            double G[3], J[3][3];
-            for (int c = 0; c < 3; ++c) {
-                double gv = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+            const int q0 = e1 * P + g1, q1 = e2 * P + g2;
+            const double w01 = d0.W[q0] * d1.W[q1];
+            for (int gg = 0; gg < NPS; ++gg) {
+                const double *sg = sb + gg * 9 * TYX;
+                double G[3], J[3][3];
+                for (int c = 0; c < 3; ++c) {
+                    double gv = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
 #pragma unroll
-                for (int s = 0; s < P; ++s) {
-                    double vb = sb[((3 * c + 0) * TY + ty) * NX + le1 + s];
-                    double vd = sb[((3 * c + 1) * TY + ty) * NX + le1 + s];
-                    double wb = sb[((3 * c + 2) * TY + ty) * NX + le1 + s];
-                    gv += b1[s] * vb;
-                    j0 += db1[s] * vb;
-                    j1 += b1[s] * vd;
-                    j2 += b1[s] * wb;
+                    for (int s = 0; s < P; ++s) {
+                        double vb = sg[((3 * c + 0) * TY + ty) * NX + le1 + s];
+                        double vd = sg[((3 * c + 1) * TY + ty) * NX + le1 + s];
+                        double wb = sg[((3 * c + 2) * TY + ty) * NX + le1 + s];
+                        gv += b1[s] * vb;
+                        j0 += db1[s] * vb;
+                        j1 += b1[s] * vd;
+                        j2 += b1[s] * wb;
+                    }
+                    G[c] = gv;
+                    J[c][0] = j0;
+                    J[c][1] = j1;
+                    J[c][2] = j2;
                 }
-                G[c] = gv;
-                J[c][0] = j0;
-                J[c][1] = j1;
-                J[c][2] = j2;
+                const int q2 = e3 * P + g3b + gg;
+                const double w = w01 * d2.W[q2];
+                const int64_t qlin = (int64_t)q0 + (int64_t)d0.Q * (q1 + (int64_t)d1.Q * q2);
+                pointwise_3d(G, J, w, qlin, q0, q1, q2, pv, o, f32);
             }
-            const int q0 = e1 * P + g1, q1 = e2 * P + g2, q2 = e3 * P + g3;
-            const double w = d0.W[q0] * d1.W[q1] * d2.W[q2];
-            const int64_t qlin = (int64_t)q0 + (int64_t)d0.Q * (q1 + (int64_t)d1.Q * q2);
-            pointwise_3d(G, J, w, qlin, q0, q1, q2, pv, o, f32);
         }
         __syncthreads();
     }
@@ -255,8 +283,14 @@ static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream
     if (pv.d == 3) {
         using TL = Tile<P>;
         dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
-        size_t lds = sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * TL::NY * TL::NX + 9 * TL::TY * TL::NX +
-                                       2 * (TL::E1 + TL::E2) * P * P);
+        constexpr size_t lds = geom3d_lds<P>();
+        static bool lds_set = false;
+        if (!lds_set && lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)geom3d_kernel<P>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lds_set = true;
+        }
         hipLaunchKernelGGL(geom3d_kernel<P>, grid, dim3(TL::NT), lds, s, pv, o);
     } else {
         int64_t nb = (pv.Q + 255) / 256;
