@@ -126,7 +126,7 @@ constexpr size_t a12_lds_bytes()
     using S = A12Shape<P, STIFF>;
     size_t a = sizeof(CT) * (size_t)(S::NSLICE + S::L1SZ);
     a = (a + 15) / 16 * 16;
-    return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * P * P);
+    return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * 2 * P * P);
 }
 
 // symmetric component of pair (i, j) in the order 00 11 22 01 02 12
@@ -157,7 +157,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     CT *l1 = cs + S::NSLICE;                            // [g2][pair][T1][W]
     double *t1B = reinterpret_cast<double *>(smem_raw + (sizeof(CT) * (S::NSLICE + S::L1SZ) + 15) / 16 * 16);
     double *t1D = t1B + P * P * XE;                     // [g1][j][XE]
-    double *t2B = t1D + P * P * XE, *t2D = t2B + P * P; // [g2][j] of the current element e2
+    // direction-2 tables [B, D][g2][j] of element e2 in buffer e2 & 1: the next
+    // element's are staged while level 2 still reads the current ones
+    double *t2buf = t1D + P * P * XE;
+    double *t2B = t2buf, *t2D = t2B + P * P;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1];
     const int tid = threadIdx.x;
@@ -201,7 +204,8 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
             }
         }
     };
-    auto store_stage = [&]() {
+    auto store_stage = [&](int e2) {
+        double *t2 = t2buf + (e2 & 1) * 2 * P * P;
 #pragma unroll
         for (int k = 0; k < S::PF; ++k) {
             const int idx = tid + k * NT;
@@ -210,7 +214,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int le1 = lq1 / P, g1 = lq1 % P;
                 cs[(r * P + g1) * XE + le1] = (CT)pf[k];
             } else if (idx < S::NSTAGE) {
-                t2B[idx - S::NSLICE] = pf[k];      // t2D follows t2B
+                t2[idx - S::NSLICE] = pf[k];
             }
         }
     };
@@ -244,10 +248,14 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     const int nitems = nrow1 * WW;
 
     load_stage(0);
-    store_stage();
+    store_stage(0);
     __syncthreads();
 
+    // per element: level 1 | barrier | level 2 while the next slice is stored
+    // (level 2 reads no slice, and the tables are double-buffered) | barrier
     for (int e2 = 0; e2 < K2; ++e2) {
+        t2B = t2buf + (e2 & 1) * 2 * P * P;
+        t2D = t2B + P * P;
         // ---------------- level 1: contract x1 for every row of the tile.
         // One lane per (pair, row m1) forms all p x2 points of the element, so
         // the table values of each (element, x1 point) serve p x2 points.
@@ -469,11 +477,8 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 for (int g = 0; g < NG; ++g) acc[k][P - 1][g] = CT(0);
             }
         }
+        if (more) store_stage(e2 + 1);
         __syncthreads();
-        if (more) {
-            store_stage();
-            __syncthreads();
-        }
     }
 }
 
