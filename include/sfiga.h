@@ -210,11 +210,19 @@ sf_status sf_batch_offsets(const sf_batch *batch, int64_t *row_off, int64_t *nnz
 /* Pattern and values of all patches into concatenated device arrays
  * (row_ptr [sum N + 1] int64 with global offsets, col_ind [sum nnz] int32
  * with global column indices, val_* [sum nnz]); every patch must have been
- * prepared for `ops` at `prec`.  The whole batch is one HIP graph launch. */
+ * prepared for `ops` at `prec`.  The d = 3 patches of each order run in
+ * persistent kernels that walk the per-patch work items; on a non-default
+ * stream the whole call is captured into one HIP graph and replayed for
+ * later calls with the same buffers.  The first call per (operator,
+ * precision) times a few tile shapes and workgroups per CU on the batch
+ * itself (writing into the outputs, which the call then rewrites) and
+ * synchronizes; the choice does not change the values.  Task lists stay
+ * allocated with the batch. */
 sf_status sf_batch_assemble(sf_batch *batch, unsigned ops, sf_precision prec, int64_t *dev_row_ptr,
                             int32_t *dev_col_ind, double *dev_val_mass, double *dev_val_stiff);
 
-/* y = blockdiag(A_b) x over the concatenated vectors, one HIP graph launch. */
+/* y = blockdiag(A_b) x over the concatenated vectors; persistent kernels,
+ * graph capture and first-call tuning as for sf_batch_assemble. */
 sf_status sf_batch_apply(sf_batch *batch, unsigned op, sf_precision prec, const double *dev_x,
                          double *dev_y);
 

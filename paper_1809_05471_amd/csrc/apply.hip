@@ -10,10 +10,11 @@
 // workgroup walks its layers in order with sliding windows of the p rows of x
 // and of partial y that the current layer touches; every stage handles all
 // p quadrature planes of the layer at once (5 barriers per layer).  The
-// coefficient tensor is the only stream that scales with Q: the next layer's
-// coefficients are loaded into registers while the current layer is
-// computed.  Partial y rows leave the window through FP64 atomics (the
-// accumulation of eq. (loc-basis-change)), because boxes share functions.
+// coefficient tensor is the only stream that scales with Q; it is read plane
+// by plane in the pointwise stage (prefetched a layer ahead only where that
+// costs no occupancy).  LZ is tuned per patch by the caller.  Partial y rows
+// leave the window through FP64 atomics (the accumulation of eq.
+// (loc-basis-change)), because boxes share functions.
 #include "kernels.h"
 
 namespace sfiga {

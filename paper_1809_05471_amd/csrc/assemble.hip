@@ -13,13 +13,17 @@
 //  asm12_kernel (levels 1 and 2): a workgroup owns one quadrature plane x3
 //    and a tile of T1 rows m1.  It walks the elements e2 of direction 2 in
 //    order; per element it stages the coefficient slice (x1 support of the
-//    tile x the p points of e2), forms level 1 for the tile's rows and all
-//    nine (i, j) pairs, and folds it into a sliding window of the p rows m2
-//    that e2 touches.  Pairs that share their direction-3 tables are summed
-//    at this point (Sec. 3.1 splitting: 4 groups BB, BD, DB, DD for the
-//    stiffness), so the level-2 partial of a plane is
+//    tile x the p points of e2) and forms level 1 for the tile's rows and
+//    the (i, j) pairs (vector ALU; (2, 1) equals (1, 2) at this level).
+//    Level 2 then adds the element's p points x2: pairs that share their
+//    direction-3 tables are summed here (Sec. 3.1 splitting: 4 groups BB,
+//    BD, DB, DD for the stiffness).  In FP64 it runs on the matrix cores
+//    (rows = slots (m2 mod p, n2 mod p), columns = (m1, n1), K = (pair, x2));
+//    in BF16 split on bf16 matrix cores with hi/lo operands; in FP32 on the
+//    vector ALU with a sliding window of the p rows m2.  An entry is written
+//    to the level-2 partial of its plane,
 //      A2[g][m2][m1][n2 - m2 + p - 1][n1 - m1 + p - 1],
-//    written to device memory once per row m2.
+//    once its last element e2 has been added.
 //
 //  asm3_kernel (level 3): one thread per level-2 entry (m1, m2, n1, n2)
 //    walks the elements e3 of a segment of rows m3 and keeps the p x p
