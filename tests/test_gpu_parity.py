@@ -318,6 +318,85 @@ def test_batched_patches(npatch, kmax, pmax, side):
                 g.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(sf.SF_FP32, TOL32), (sf.SF_BF16_SPLIT, TOLBF)])
+def test_batched_mixed_precision(prec, tol):
+    """The batched path in the reduced-precision modes (the 512-patch workload
+    runs FP32 contractions), on a side stream with graph replay."""
+    import torch
+    from tests.gpu_util import side_ctx
+    c, stream = side_ctx()
+    Ks, ps = inputs.batched_draw(12, seed=5, kmin=2, kmax=6, pmin=2, pmax=5)
+    with torch.cuda.stream(stream):
+        patches, refs = [], []
+        for b in range(12):
+            kn, ctrl, x = inputs.batched_patch(b, Ks[b], ps[b])
+            g = GpuPatch(kn, int(ps[b]), ctrl, context=c)
+            g.prepare(prec=prec)
+            patches.append(g)
+            P = oracle.Problem(kn, int(ps[b]), ctrl)
+            rp_o, ci_o = P.pattern()
+            refs.append({op: P.assemble(op, pattern=(rp_o, ci_o))[2] for op in (sf.SF_MASS, sf.SF_STIFF)})
+        try:
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            ro, zo = sf.sf_batch_offsets(c, bt, 12)
+            Z = int(zo[-1])
+            rp = torch.empty(int(ro[-1]) + 1, dtype=torch.int64, device="cuda")
+            ci = torch.empty(Z, dtype=torch.int32, device="cuda")
+            vm = torch.empty(Z, dtype=torch.float64, device="cuda")
+            vs = torch.empty(Z, dtype=torch.float64, device="cuda")
+            for rep in range(2):
+                vs.fill_(float("nan"))
+                sf.sf_batch_assemble(c, bt, sf.SF_MASS | sf.SF_STIFF, prec, rp, ci, vm, vs)
+                stream.synchronize()
+                vmn, vsn = vm.cpu().numpy(), vs.cpu().numpy()
+                for b in range(12):
+                    z0, z1 = zo[b], zo[b + 1]
+                    assert err_A(vmn[z0:z1], refs[b][sf.SF_MASS]) <= tol, (rep, b)
+                    assert err_A(vsn[z0:z1], refs[b][sf.SF_STIFF]) <= tol, (rep, b)
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
+
+
+def test_batched_equals_single_patch():
+    """Tile shapes (tuned separately for the single-patch and the batched
+    launches) do not change the summation order of any entry: the batched
+    FP64 assembly equals the single-patch one to the last bits (the two
+    launches are separate compilations of the same block code, so only
+    contraction of multiply-adds may differ)."""
+    import torch
+    from tests.gpu_util import side_ctx
+    c, stream = side_ctx()
+    Ks, ps = inputs.batched_draw(8, seed=9, kmin=3, kmax=9, pmin=2, pmax=5)
+    with torch.cuda.stream(stream):
+        patches = []
+        for b in range(8):
+            kn, ctrl, _ = inputs.batched_patch(b, Ks[b], ps[b])
+            g = GpuPatch(kn, int(ps[b]), ctrl, coef=("sinprod", 0.5), context=c)
+            g.prepare(sf.SF_STIFF)
+            patches.append(g)
+        try:
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            ro, zo = sf.sf_batch_offsets(c, bt, 8)
+            Z = int(zo[-1])
+            rp = torch.empty(int(ro[-1]) + 1, dtype=torch.int64, device="cuda")
+            ci = torch.empty(Z, dtype=torch.int32, device="cuda")
+            vs = torch.empty(Z, dtype=torch.float64, device="cuda")
+            sf.sf_batch_assemble(c, bt, sf.SF_STIFF, sf.SF_FP64, rp, ci, None, vs)
+            stream.synchronize()
+            vsn = vs.cpu().numpy()
+            for b, g in enumerate(patches):
+                v = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+                sf.sf_assemble(c, g.h, sf.SF_STIFF, sf.SF_FP64, val_stiff=v)
+                stream.synchronize()
+                assert err_A(vsn[zo[b]:zo[b + 1]], v.cpu().numpy()) <= 4e-16, b
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
+
+
 def test_error_paths():
     kn, ctrl = inputs.identity_geometry((3, 3, 3), 3)
     folded = ctrl.copy()
