@@ -20,17 +20,21 @@
 //    BD, DB, DD for the stiffness).  In FP64 it runs on the matrix cores
 //    (rows = slots (m2 mod p, n2 mod p), columns = (m1, n1), K = (pair, x2));
 //    in BF16 split on bf16 matrix cores with hi/lo operands; in FP32 on the
-//    vector ALU with a sliding window of the p rows m2.  An entry is written
-//    to the level-2 partial of its plane,
-//      A2[g][m2][m1][n2 - m2 + p - 1][n1 - m1 + p - 1],
+//    vector ALU with a sliding window of the p rows m2.  Both operators are
+//    symmetric, so only the entries with n2 > m2, or n2 == m2 and n1 >= m1,
+//    are kept (the partial of group (a, b) at (n12, m12) is that of (b, a)
+//    at (m12, n12)): ((p - 1)(2p - 1) + p of the (2p - 1)^2 windows).  A
+//    kept entry is written to the level-2 partial of its plane,
+//      A2[g][m2][m1][kh(n1 - m1 + p - 1, n2 - m2 + p - 1)],
 //    once its last element e2 has been added.
 //
-//  asm3_kernel (level 3): one thread per level-2 entry (m1, m2, n1, n2)
+//  asm3_kernel (level 3): one thread per kept level-2 entry (m1, m2, n1, n2)
 //    walks the elements e3 of a segment of rows m3 and keeps the p x p
 //    window w[r][s] of entries (m3, n3) = (e3 + r, e3 + s).  After element
 //    e3 the entries with r = 0 or s = 0 are complete and go straight to
-//    their CSR slots; the window then shifts along the diagonal.  Each
-//    value is written once, in FP64 (no atomics, deterministic).
+//    their CSR slots, together with their mirrors (n, m) off the diagonal
+//    m12 == n12; the window then shifts along the diagonal.  Each value is
+//    written once, in FP64 (no atomics, deterministic).
 //
 // The level-2 partials of a chunk of element layers live in a device
 // workspace; when the whole patch does not fit, chunks of at least p - 1
@@ -102,9 +106,36 @@ __device__ __forceinline__ int group_pair(int g, int t)
 }
 __host__ __device__ constexpr int group_npairs(int g) { return g == 0 ? 4 : (g == 3 ? 1 : 2); }
 
+// Both operators are symmetric (C_ij = C_ji), so the level-2 partial of group
+// (a, b) at (m12, n12) is the partial of group (b, a) at (n12, m12): only the
+// windows with n2 > m2, or n2 == m2 and n1 >= m1, are formed and stored.
+// Window kh < p is (c1, c2) = (p - 1 + kh, p - 1); window kh >= p is
+// c1 = (kh - p) % W, c2 = p + (kh - p) / W.
+__host__ __device__ constexpr int half_windows(int P) { return (P - 1) * (2 * P - 1) + P; }
+template <int P>
+__device__ __forceinline__ int half_index(int c1, int c2)
+{
+    constexpr int W = 2 * P - 1;
+    if (c2 > P - 1) return P + (c2 - P) * W + c1;
+    return (c2 == P - 1 && c1 >= P - 1) ? c1 - (P - 1) : -1;
+}
+template <int P>
+__device__ __forceinline__ void half_window(int kh, int &c1, int &c2)
+{
+    constexpr int W = 2 * P - 1;
+    if (kh < P) {
+        c1 = P - 1 + kh;
+        c2 = P - 1;
+    } else {
+        c1 = (kh - P) % W;
+        c2 = P + (kh - P) / W;
+    }
+}
+
 template <int P, bool STIFF>
 struct A12Shape {
     static constexpr int W = 2 * P - 1;          // band width per direction
+    static constexpr int NH = half_windows(P);    // stored level-2 windows (c1, c2) per row
     static constexpr int NP = STIFF ? 9 : 1;     // (i, j) pairs
     static constexpr int NG = STIFF ? 4 : 1;     // groups sharing the direction-3 tables
     static constexpr int NCOMP = STIFF ? 6 : 1;  // symmetric coefficient components
@@ -114,7 +145,7 @@ struct A12Shape {
     static constexpr int NSLICE = NCOMP * P * P * XE;        // coefficient slice of one element e2
     static constexpr int NSTAGE = NSLICE + 2 * P * P;        // + its direction-2 tables
     static constexpr int PF = (NSTAGE + NT - 1) / NT;        // staged values per thread
-    static constexpr int ITEMS = (T1 * W * W + NT - 1) / NT;  // level-2 entries per thread
+    static constexpr int ITEMS = (T1 * NH + NT - 1) / NT;     // level-2 entries per thread
     static constexpr int L1SZ = P * NP * T1 * W;             // level-1 results of one element
     // level 2 on the matrix cores (FP64): slots (m2 mod p, n2 mod p) as rows,
     // 16 columns (m1, c1) per wave, K = (pair of the group, x2 point)
@@ -142,7 +173,8 @@ __device__ __forceinline__ int comp3(int i, int j)
 }
 
 // Levels 1 and 2 of plane x3 = q3base + by for the tile bx of rows m1.
-// A2 layout: [plane - q3base][g][m2][m1][c2][c1], c = n - m + p - 1.
+// A2 layout: [plane - q3base][g][m2][m1][kh], kh the stored window of
+// (c1, c2), c = n - m + p - 1.
 // L2M: level 2 on the vector ALU (0), on FP64 matrix cores (1), on bf16
 // matrix cores with split operands and FP32 accumulation (2).
 template <int P, bool STIFF, typename CT, int L2M>
@@ -151,7 +183,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
 {
     using S = A12Shape<P, STIFF>;
     constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
-    constexpr int WW = W * W;
+    constexpr int NH = S::NH;
     constexpr int NP1 = STIFF ? 8 : 1;                  // pairs formed at level 1
     // x2 points per level-1 lane (a divisor of p, bounded by registers)
     constexpr int G2B = (P == 2 || P == 6 || P == 8) ? 2 : 1;
@@ -174,7 +206,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     const int pl = by;
     const int q3 = q3base + pl;
     const int Q0 = d0.Q, Q1 = d1.Q, N1 = d0.N, N2 = d1.N, K1 = d0.K, K2 = d1.K;
-    const int64_t rowsz = (int64_t)N1 * WW;             // one row m2 of A2
+    const int64_t rowsz = (int64_t)N1 * NH;             // one row m2 of A2
     CT *A2p = A2 + (int64_t)pl * NG * N2 * rowsz;
 
     // direction-1 tables of the tile's elements, [g1][j][le1] (zeros outside the mesh)
@@ -249,7 +281,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
         for (int r = 0; r < P; ++r)
 #pragma unroll
             for (int g = 0; g < NG; ++g) acc[k][r][g] = CT(0);
-    const int nitems = nrow1 * WW;
+    const int nitems = nrow1 * NH;
 
     load_stage(0);
     store_stage(0);
@@ -349,7 +381,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 }
                 // entries whose last element is e2 (r == 0 or s == 0), all after the last element
                 const int lm1 = col / W, c1 = col % W;
-                CT *dst = A2p + (int64_t)(b1 + lm1) * WW + c1;
+                CT *dst = A2p + (int64_t)(b1 + lm1) * NH;
 #pragma unroll
                 for (int rb = 0; rb < S::MB; ++rb)
 #pragma unroll
@@ -358,10 +390,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                         const int ms = i / P, ns = i % P;
                         if (i < S::NSLOT && (last || ms == ph || ns == ph)) {
                             const int m2 = e2 + (ms - ph + P) % P, n2 = e2 + (ns - ph + P) % P;
-                            const int c2 = n2 - m2 + P - 1;
+                            const int kh = half_index<P>(c1, n2 - m2 + P - 1);
 #pragma unroll
                             for (int g = 0; g < NG; ++g) {
-                                if (colok) dst[((int64_t)g * N2 + m2) * rowsz + c2 * W] = macc[nb][g][rb][v];
+                                if (colok && kh >= 0) dst[((int64_t)g * N2 + m2) * rowsz + kh] = macc[nb][g][rb][v];
                                 macc[nb][g][rb][v] = 0.0;
                             }
                         }
@@ -420,7 +452,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                     }
                 }
                 const int lm1 = col / W, c1 = col % W;
-                CT *dst = A2p + (int64_t)(b1 + lm1) * WW + c1;
+                CT *dst = A2p + (int64_t)(b1 + lm1) * NH;
 #pragma unroll
                 for (int rb = 0; rb < S::MB; ++rb)
 #pragma unroll
@@ -429,10 +461,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                         const int ms = i / P, ns = i % P;
                         if (i < S::NSLOT && (last || ms == ph || ns == ph)) {
                             const int m2 = e2 + (ms - ph + P) % P, n2 = e2 + (ns - ph + P) % P;
-                            const int c2 = n2 - m2 + P - 1;
+                            const int kh = half_index<P>(c1, n2 - m2 + P - 1);
 #pragma unroll
                             for (int g = 0; g < NG; ++g) {
-                                if (colok) dst[((int64_t)g * N2 + m2) * rowsz + c2 * W] = (CT)facc[nb][g][rb][v];
+                                if (colok && kh >= 0) dst[((int64_t)g * N2 + m2) * rowsz + kh] = (CT)facc[nb][g][rb][v];
                                 facc[nb][g][rb][v] = 0.f;
                             }
                         }
@@ -443,7 +475,9 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
             for (int k = 0; k < (L2M == 0 ? S::ITEMS : 1); ++k) {
                 const int it = tid + k * NT;
                 if (it >= nitems) continue;
-                const int c1 = it % W, c2 = (it / W) % W, lm1 = it / WW;
+                const int lm1 = it / NH;
+                int c1, c2;
+                half_window<P>(it % NH, c1, c2);
 #pragma unroll 1
                 for (int g2 = 0; g2 < P; ++g2) {
                     CT L[NP];
@@ -466,7 +500,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                     }
                 }
                 // row m2 = e2 is complete (and every row of the window after the last element)
-                CT *dst = A2p + (int64_t)b1 * WW + it;
+                CT *dst = A2p + (int64_t)b1 * NH + it;
 #pragma unroll
                 for (int r = 0; r < P; ++r) {
                     if (r > 0 && !last) break;
@@ -494,39 +528,113 @@ __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchVi
 }
 
 // Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
-// segment seg0 + bz (length L).  One thread per level-2 entry
-// (m1, n1, m2 = by, n2); block bx covers 256 entries of the row m2.
+// segment seg0 + bz (length L).  One thread per stored level-2 window
+// (m1, n1, m2 = by, n2); block bx covers 256 windows of the row m2.
+//
+// A thread stores its own entries (m, n) directly: consecutive threads hold
+// consecutive columns of a row.  The mirrors (n, m) off the diagonal
+// m12 == n12 go through LDS: the windows of a block are ordered once by
+// mirror position, key (n1, c2, m1 - n1 + p - 1), with a counting sort, and
+// after each element lane l stores the mirror values of the l-th window in
+// that order, so a wavefront writes runs of up to 2p - 1 consecutive columns
+// (for fixed n1 and c2 the mirror column advances with m1).
+template <int P>
+struct A3Shape {
+    static constexpr int W = 2 * P - 1, NH = half_windows(P);
+    static constexpr int NJ = 2 * P - 1;                        // entries per element and window
+    static constexpr int NROW = 255 / NH + 2;                   // rows m1 a block touches (max)
+    static constexpr int NKEY = (NROW + 2 * P - 2) * P * W;     // mirror keys (n1, c2, k)
+    static_assert(NKEY <= NJ * 256 * 2, "key table fits in the mirror buffer");
+};
+
 template <int P, bool STIFF, typename CT>
 __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__restrict__ A2, double *__restrict__ vals,
                                            int s0, int s1, int L, int seg0, int bx, int by, int bz)
 {
-    constexpr int W = 2 * P - 1, WW = W * W, NG = STIFF ? 4 : 1;
+    using S3 = A3Shape<P>;
+    constexpr int NH = S3::NH, NG = STIFF ? 4 : 1, NJ = S3::NJ;
+    __shared__ double mv[NJ][256];          // mirror values of one element (the setup's tables first)
+    __shared__ int inv[256];                // lane -> window in mirror order
+    __shared__ int wsum[4];
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
-    const int N1 = d0.N, N2 = d1.N;
-    const int64_t rowsz = (int64_t)N1 * WW;
-    const int it = bx * 256 + threadIdx.x;
-    if (it >= rowsz) return;
-    const int m2 = by;
-    const int c1 = it % W, c2 = (it / W) % W, m1 = it / WW;
-    const int n1 = m1 + c1 - P + 1, n2 = m2 + c2 - P + 1;
-    if (n1 < 0 || n1 >= N1 || n2 < 0 || n2 >= N2) return;
+    const int N1 = d0.N, N2 = d1.N, N3 = d2.N;
+    const int64_t rowsz = (int64_t)N1 * NH;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t it0 = (int64_t)bx * 256;
     const int a3 = (seg0 + bz) * L;
     const int ebeg = max(s0, a3 - P + 1), eend = min(s1 - 1, a3 + L - 1);
-    if (ebeg > eend) return;
+    if (ebeg > eend) return;                                    // uniform over the block
+
+    const int64_t it = it0 + tid;
+    const int m2 = by;
+    const int m1 = (int)(min(it, rowsz - 1) / NH);
+    int c1, c2;
+    half_window<P>((int)(min(it, rowsz - 1) % NH), c1, c2);
+    const int n1 = m1 + c1 - P + 1, n2 = m2 + c2 - P + 1;
+    const bool active = it < rowsz && n1 >= 0 && n1 < N1 && n2 >= 0 && n2 < N2;
+    const bool mirror = active && (c1 != P - 1 || c2 != P - 1);
 
     const RowIndex &ri = pv.ri;
-    const int64_t len1 = band_len(m1, P, N1), len2 = band_len(m2, P, N2);
-    const int64_t R12 = ri.S[1][m2] * ri.T[0] + len2 * ri.S[0][m1];
-    const int64_t off12 = (n1 - band_lo(m1, P)) + (int64_t)(n2 - band_lo(m2, P)) * len1;
-    const int64_t len12 = len1 * len2, T21 = ri.T[1] * ri.T[0];
-    const int N3 = d2.N;
-    auto emit = [&](int m3, int n3, double v) {
-        if (m3 < a3 || m3 >= a3 + L || n3 < 0 || n3 >= N3) return;
-        const int64_t pos = ri.S[2][m3] * T21 + (int64_t)band_len(m3, P, N3) * R12 + off12 +
-                            (int64_t)(n3 - band_lo(m3, P)) * len12;
-        if (s0 > 0 && max(m3, n3) - P + 1 < s0) v += vals[pos];   // partial sum of the previous chunk
-        vals[pos] = v;
-    };
+    const int64_t T21 = ri.T[1] * ri.T[0];
+    int64_t R12 = 0, off12 = 0, len12 = 0, mR12 = 0, moff12 = 0, mlen12 = 0;
+    if (active) {
+        const int64_t len1 = band_len(m1, P, N1), len2 = band_len(m2, P, N2);
+        R12 = ri.S[1][m2] * ri.T[0] + len2 * ri.S[0][m1];
+        off12 = (n1 - band_lo(m1, P)) + (int64_t)(n2 - band_lo(m2, P)) * len1;
+        len12 = len1 * len2;
+        // mirror: row (n1, n2, n3), column (m1, m2, m3)
+        const int64_t ml1 = band_len(n1, P, N1), ml2 = band_len(n2, P, N2);
+        mR12 = ri.S[1][n2] * ri.T[0] + ml2 * ri.S[0][n1];
+        moff12 = (m1 - band_lo(n1, P)) + (int64_t)(m2 - band_lo(n2, P)) * ml1;
+        mlen12 = ml1 * ml2;
+    }
+
+    // ---- mirror order: counting sort of the keys (n1 - n1min, c2 - p + 1, k)
+    int *cnt = reinterpret_cast<int *>(&mv[0][0]);
+    const int m1a = (int)(it0 / NH);
+    const int m1b = (int)(min(it0 + 255, rowsz - 1) / NH);
+    const int nkey = (m1b - m1a + 2 * P - 1) * P * S3::W;
+    const int key = mirror ? ((n1 - (m1a - P + 1)) * P + (c2 - P + 1)) * S3::W + (m1 - n1 + P - 1) : -1;
+    for (int i = tid; i < nkey; i += 256) cnt[i] = 0;
+    __syncthreads();
+    if (mirror) cnt[key] = 1;
+    __syncthreads();
+    const int per = (nkey + 255) / 256;
+    int loc = 0;
+    for (int k = 0; k < per; ++k) {
+        const int i = tid * per + k;
+        if (i < nkey) loc += cnt[i];
+    }
+    int incl = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - loc;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    const int nmir = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    for (int k = 0; k < per; ++k) {
+        const int i = tid * per + k;
+        if (i < nkey) {
+            const int v = cnt[i];
+            cnt[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    if (mirror) inv[cnt[key]] = tid;
+    __syncthreads();
+    int64_t *cst = reinterpret_cast<int64_t *>(&mv[0][0]);     // [3][256] mirror row constants
+    cst[tid] = mR12;
+    cst[256 + tid] = moff12;
+    cst[512 + tid] = mlen12;
+    __syncthreads();
+    const int wsrc = tid < nmir ? inv[tid] : 0;                 // this lane stores the mirrors of window wsrc
+    const int64_t wR12 = cst[wsrc], woff12 = cst[256 + wsrc], wlen12 = cst[512 + wsrc];
+    __syncthreads();
 
     double w[P][P];
 #pragma unroll
@@ -534,18 +642,18 @@ __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__rest
 #pragma unroll
         for (int s = 0; s < P; ++s) w[r][s] = 0.0;
     const int64_t gstride = (int64_t)N2 * rowsz;         // next group of the same plane
-    const CT *src = A2 + (int64_t)m2 * rowsz + it + (int64_t)(ebeg - s0) * P * NG * gstride;
+    const CT *src = A2 + (int64_t)m2 * rowsz + (active ? it : 0) + (int64_t)(ebeg - s0) * P * NG * gstride;
     // level-2 values of the next plane are loaded one plane ahead
     CT G[NG], Gn[NG];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) Gn[g] = src[g * gstride];
+    for (int g = 0; g < NG; ++g) Gn[g] = active ? src[g * gstride] : CT(0);
     for (int e3 = ebeg; e3 <= eend; ++e3) {
 #pragma unroll 1
         for (int g3 = 0; g3 < P; ++g3) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) G[g] = Gn[g];
             src += NG * gstride;
-            if (g3 + 1 < P || e3 < eend) {
+            if (active && (g3 + 1 < P || e3 < eend)) {
 #pragma unroll
                 for (int g = 0; g < NG; ++g) Gn[g] = src[g * gstride];
             }
@@ -575,18 +683,57 @@ __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__rest
                 }
             }
         }
-        // entries whose last element is e3: (e3, e3 + s) and (e3 + r, e3)
+        // entries whose last element is e3: j < p is (e3, e3 + j), j >= p is
+        // (e3 + j - p + 1, e3); the row m3 must lie in the segment
+        const int64_t b0 = ri.S[2][e3] * T21;
+        const int64_t l0 = band_len(e3, P, N3), lo0 = band_lo(e3, P);
 #pragma unroll
-        for (int s = 0; s < P; ++s) emit(e3, e3 + s, w[0][s]);
-#pragma unroll
-        for (int r = 1; r < P; ++r) emit(e3 + r, e3, w[r][0]);
+        for (int j = 0; j < NJ; ++j) {
+            const int m3 = j < P ? e3 : e3 + j - P + 1, n3 = j < P ? e3 + j : e3;
+            if (m3 < a3 || m3 >= a3 + L || n3 >= N3) continue;    // uniform
+            if (active) {
+                const int64_t pos = j < P ? b0 + l0 * R12 + off12 + (n3 - lo0) * len12
+                                          : ri.S[2][m3] * T21 + band_len(m3, P, N3) * R12 + off12 +
+                                                (int64_t)(n3 - band_lo(m3, P)) * len12;
+                double v = j < P ? w[0][j] : w[j - P + 1][0];
+                if (s0 > 0 && max(m3, n3) - P + 1 < s0) v += vals[pos];   // partial sum of the previous chunk
+                vals[pos] = v;
+                mv[j][tid] = v;
+            }
+        }
         if (e3 == s1 - 1) {
-            // end of the chunk: the rest is complete (last layer) or partial
+            // end of the chunk: the rest of the window is complete (last layer)
+            // or partial; mirrors go straight to memory (once per chunk)
 #pragma unroll
             for (int r = 1; r < P; ++r)
 #pragma unroll
-                for (int s = 1; s < P; ++s) emit(e3 + r, e3 + s, w[r][s]);
+                for (int s = 1; s < P; ++s) {
+                    const int m3 = e3 + r, n3 = e3 + s;
+                    if (!active || m3 < a3 || m3 >= a3 + L || n3 >= N3) continue;
+                    const int64_t pos = ri.S[2][m3] * T21 + band_len(m3, P, N3) * R12 + off12 +
+                                        (int64_t)(n3 - band_lo(m3, P)) * len12;
+                    double v = w[r][s];
+                    if (s0 > 0 && max(m3, n3) - P + 1 < s0) v += vals[pos];
+                    vals[pos] = v;
+                    if (mirror)
+                        vals[ri.S[2][n3] * T21 + band_len(n3, P, N3) * mR12 + moff12 +
+                             (int64_t)(m3 - band_lo(n3, P)) * mlen12] = v;
+                }
         }
+        __syncthreads();
+        if (tid < nmir) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int m3 = j < P ? e3 : e3 + j - P + 1, n3 = j < P ? e3 + j : e3;
+                if (m3 < a3 || m3 >= a3 + L || n3 >= N3) continue;
+                // mirror of (m3, n3): row n3, column m3
+                const int64_t pos = j < P ? ri.S[2][n3] * T21 + band_len(n3, P, N3) * wR12 + woff12 +
+                                                (int64_t)(m3 - band_lo(n3, P)) * wlen12
+                                          : b0 + l0 * wR12 + woff12 + (m3 - lo0) * wlen12;
+                vals[pos] = mv[j][wsrc];
+            }
+        }
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r + 1 < P; ++r)
 #pragma unroll
@@ -688,8 +835,9 @@ __global__ void asm_small_kernel(PatchView pv, const CT *__restrict__ C, double 
 
 static size_t a2_plane_bytes(const PatchView &pv, int op, Prec prec)
 {
-    const int W = 2 * pv.P - 1, NG = op == 2 ? 4 : 1;
-    return (size_t)NG * pv.dir[1].N * pv.dir[0].N * W * W * (prec == Prec::F64 ? sizeof(double) : sizeof(float));   // BF16X3: FP32
+    const int NG = op == 2 ? 4 : 1;
+    return (size_t)NG * pv.dir[1].N * pv.dir[0].N * half_windows(pv.P) *
+           (prec == Prec::F64 ? sizeof(double) : sizeof(float));   // BF16X3: FP32
 }
 
 // element layers per chunk for a workspace of the given size (0: too small)
@@ -748,10 +896,10 @@ void asm12_blocks(const PatchView &pv, int t1, int &gx, int &gy, int &T1r)
 
 void asm3_blocks(const PatchView &pv, int seg, int &gx, int &gy, int &gz, int &L)
 {
-    const int W = 2 * pv.P - 1, N3 = pv.dir[2].N;
+    const int N3 = pv.dir[2].N;
     const int nseg = (N3 + (seg > 0 ? seg : 16) - 1) / (seg > 0 ? seg : 16);
     L = (N3 + nseg - 1) / nseg;
-    gx = (int)(((int64_t)pv.dir[0].N * W * W + 255) / 256);
+    gx = (int)(((int64_t)pv.dir[0].N * half_windows(pv.P) + 255) / 256);
     gy = pv.dir[1].N;
     gz = nseg;
 }
@@ -823,6 +971,7 @@ __global__ __launch_bounds__(256) void asm3_persistent(TaskList tl)
         const int64_t r = l / T.gx;
         asm3_block<P, STIFF, CT>(T.pv, (const CT *)T.ws, T.out, 0, T.pv.dir[2].K, T.arg, 0, bx, (int)(r % T.gy),
                                  (int)(r / T.gy));
+        __syncthreads();   // LDS of the next block
     }
 }
 
