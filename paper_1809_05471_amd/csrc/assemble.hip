@@ -527,6 +527,13 @@ __global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchVi
     asm12_block<P, STIFF, CT, L2M>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
 }
 
+// Load of a value every lane reads at the same address from memory the kernel
+// does not write (the 1D tables): a scalar load.
+__device__ __forceinline__ double ld_uniform(const double *p)
+{
+    return *(const __attribute__((address_space(4))) double *)p;
+}
+
 // Level 3 for the chunk of elements [s0, s1) in direction 3, rows m3 of the
 // segment seg0 + bz (length L).  One thread per stored level-2 window
 // (m1, n1, m2 = by, n2); block bx covers 256 windows of the row m2.
@@ -657,7 +664,14 @@ __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__rest
 #pragma unroll
                 for (int g = 0; g < NG; ++g) Gn[g] = src[g * gstride];
             }
-            const double *tB = d2.B + ((int64_t)e3 * P + g3) * P, *tD = d2.D + ((int64_t)e3 * P + g3) * P;
+            // table values of the plane: uniform, read through the scalar cache so
+            // that they do not queue behind the level-2 loads in flight
+            double tB[P], tD[P];
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                tB[s] = ld_uniform(d2.B + ((int64_t)e3 * P + g3) * P + s);
+                tD[s] = STIFF ? ld_uniform(d2.D + ((int64_t)e3 * P + g3) * P + s) : 0.0;
+            }
             if constexpr (STIFF) {
                 double uB[P], uD[P];
 #pragma unroll
@@ -743,11 +757,29 @@ __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__rest
     }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each with its
+// own L2.  Give every XCD a contiguous range of tiles instead, so that the
+// blocks of neighbouring rows m2, which write parts of the same CSR rows
+// (entries and mirrors), share one L2 and their partial lines merge there.
+__device__ __forceinline__ void xcd_tile(int &bx, int &by, int &bz)
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int nb = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    const int t = x * q + min(x, r) + b / 8;
+    bx = t % gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+}
+
 template <int P, bool STIFF, typename CT>
 __global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__restrict__ A2, double *__restrict__ vals,
                                                    int s0, int s1, int L, int seg0)
 {
-    asm3_block<P, STIFF, CT>(pv, A2, vals, s0, s1, L, seg0, blockIdx.x, blockIdx.y, blockIdx.z);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    asm3_block<P, STIFF, CT>(pv, A2, vals, s0, s1, L, seg0, bx, by, bz);
 }
 
 // ------------------------------------------------------------------ d <= 2
