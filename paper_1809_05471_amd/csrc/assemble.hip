@@ -141,6 +141,12 @@ struct A12Shape {
     static constexpr int NCOMP = STIFF ? 6 : 1;  // symmetric coefficient components
     static constexpr int NT = A12Cfg<P>::NT;
     static constexpr int T1 = A12Cfg<P>::T1;     // rows m1 per tile (max)
+    // waves per SIMD the register allocation must allow: two workgroups per CU
+    // for p <= 4 (their LDS holds two), one above
+    static constexpr int WPE = P <= 4 ? 2 * NT / 256 : NT / 256;
+    // completed level-2 rows go through an LDS row buffer (p <= 4; above, the
+    // extra LDS and registers cost more than the waits they remove)
+    static constexpr bool DEFER = P <= 4;
     static constexpr int XE = T1 + P - 1;        // direction-1 elements touching the tile
     static constexpr int NSLICE = NCOMP * P * P * XE;        // coefficient slice of one element e2
     static constexpr int NSTAGE = NSLICE + 2 * P * P;        // + its direction-2 tables
@@ -161,7 +167,8 @@ constexpr size_t a12_lds_bytes()
     using S = A12Shape<P, STIFF>;
     size_t a = sizeof(CT) * (size_t)(S::NSLICE + S::L1SZ);
     a = (a + 15) / 16 * 16;
-    return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * 2 * P * P);
+    return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * 2 * P * P) +
+           (S::DEFER ? sizeof(CT) * (size_t)S::NG * S::T1 * S::NH : 0);
 }
 
 // symmetric component of pair (i, j) in the order 00 11 22 01 02 12
@@ -197,6 +204,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     // element's are staged while level 2 still reads the current ones
     double *t2buf = t1D + P * P * XE;
     double *t2B = t2buf, *t2D = t2B + P * P;
+    // row m2 = e2 of the level-2 partials ([g][m1][kh]), complete after element
+    // e2; written to A2 after the next barrier, away from the loads of the
+    // stage (a load's first use waits for every memory operation before it)
+    CT *rowbuf = reinterpret_cast<CT *>(t2buf + 2 * 2 * P * P);
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1];
     const int tid = threadIdx.x;
@@ -219,8 +230,13 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     }
 
     // staged values of one element e2: coefficient slice (global order comp,
-    // g2, x1 with x1 fastest) followed by the element's direction-2 tables
-    double pf[S::PF];          // slice values (exact in double for either CT) and table values
+    // g2, x1 with x1 fastest) followed by the element's direction-2 tables.
+    // The loaded values are not touched until they are stored to LDS (masking
+    // included): an instruction that reads a load's result waits for it, and
+    // for every memory operation issued before it, the A2 stores among them.
+    static_assert(2 * P * P <= NT, "at most one table value per thread");
+    CT sv[S::PF];              // coefficient slice values as loaded
+    double tv = 0.0;           // this thread's table value
     auto load_stage = [&](int e2) {
         const CT *base = C + (int64_t)q3 * NCOMP * Q1 * Q0;
 #pragma unroll
@@ -231,12 +247,11 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int g2 = r % P, comp = r / P;
                 const int q0 = eb1 * P + lq1, q1 = e2 * P + g2;
                 const bool ok = q0 >= 0 && q0 < Q0;
-                const CT v = base[ok ? ((int64_t)comp * Q1 + q1) * Q0 + q0 : 0];
-                pf[k] = ok ? (double)v : 0.0;
+                sv[k] = base[ok ? ((int64_t)comp * Q1 + q1) * Q0 + q0 : 0];
             } else if (idx < S::NSTAGE) {
                 const int t = idx - S::NSLICE;
                 const int which = t / (P * P), gj = t % (P * P);
-                pf[k] = (which ? d1.D : d1.B)[(int64_t)e2 * P * P + gj];
+                tv = (which ? d1.D : d1.B)[(int64_t)e2 * P * P + gj];
             }
         }
     };
@@ -248,9 +263,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
             if (idx < S::NSLICE) {
                 const int lq1 = idx % (XE * P), r = idx / (XE * P);
                 const int le1 = lq1 / P, g1 = lq1 % P;
-                cs[(r * P + g1) * XE + le1] = (CT)pf[k];
+                const int q0 = eb1 * P + lq1;
+                cs[(r * P + g1) * XE + le1] = (q0 >= 0 && q0 < Q0) ? sv[k] : CT(0);
             } else if (idx < S::NSTAGE) {
-                t2[idx - S::NSLICE] = pf[k];
+                t2[idx - S::NSLICE] = tv;
             }
         }
     };
@@ -283,6 +299,14 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
             for (int g = 0; g < NG; ++g) acc[k][r][g] = CT(0);
     const int nitems = nrow1 * NH;
 
+    auto flush_row = [&](int e) {
+        const int n = nrow1 * NH;
+        for (int i = tid; i < NG * n; i += NT) {
+            const int g = i / n, rem = i - g * n;
+            A2p[((int64_t)g * N2 + e) * rowsz + (int64_t)b1 * NH + rem] = rowbuf[i];
+        }
+    };
+
     load_stage(0);
     store_stage(0);
     __syncthreads();
@@ -292,6 +316,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     for (int e2 = 0; e2 < K2; ++e2) {
         t2B = t2buf + (e2 & 1) * 2 * P * P;
         t2D = t2B + P * P;
+        if (S::DEFER && e2 > 0) flush_row(e2 - 1);
         // ---------------- level 1: contract x1 for every row of the tile.
         // One lane per (pair, row m1) forms all p x2 points of the element, so
         // the table values of each (element, x1 point) serve p x2 points.
@@ -393,7 +418,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                             const int kh = half_index<P>(c1, n2 - m2 + P - 1);
 #pragma unroll
                             for (int g = 0; g < NG; ++g) {
-                                if (colok && kh >= 0) dst[((int64_t)g * N2 + m2) * rowsz + kh] = macc[nb][g][rb][v];
+                                if (colok && kh >= 0) {
+                                    if (S::DEFER && ms == ph) rowbuf[(g * nrow1 + lm1) * NH + kh] = macc[nb][g][rb][v];
+                                    else dst[((int64_t)g * N2 + m2) * rowsz + kh] = macc[nb][g][rb][v];   // last element
+                                }
                                 macc[nb][g][rb][v] = 0.0;
                             }
                         }
@@ -464,7 +492,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                             const int kh = half_index<P>(c1, n2 - m2 + P - 1);
 #pragma unroll
                             for (int g = 0; g < NG; ++g) {
-                                if (colok && kh >= 0) dst[((int64_t)g * N2 + m2) * rowsz + kh] = (CT)facc[nb][g][rb][v];
+                                if (colok && kh >= 0) {
+                                    if (S::DEFER && ms == ph) rowbuf[(g * nrow1 + lm1) * NH + kh] = (CT)facc[nb][g][rb][v];
+                                    else dst[((int64_t)g * N2 + m2) * rowsz + kh] = (CT)facc[nb][g][rb][v];   // last element
+                                }
                                 facc[nb][g][rb][v] = 0.f;
                             }
                         }
@@ -500,12 +531,20 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                     }
                 }
                 // row m2 = e2 is complete (and every row of the window after the last element)
-                CT *dst = A2p + (int64_t)b1 * NH + it;
+                if constexpr (S::DEFER) {
 #pragma unroll
-                for (int r = 0; r < P; ++r) {
-                    if (r > 0 && !last) break;
+                    for (int g = 0; g < NG; ++g) rowbuf[g * nrow1 * NH + it] = acc[k][0][g];
+                }
+                {
+                    // without the row buffer row e2 goes straight to A2; the rows
+                    // after it only once the last element has been added
+                    CT *dst = A2p + (int64_t)b1 * NH + it;
 #pragma unroll
-                    for (int g = 0; g < NG; ++g) dst[((int64_t)g * N2 + e2 + r) * rowsz] = acc[k][r][g];
+                    for (int r = S::DEFER ? 1 : 0; r < P; ++r) {
+                        if (r > 0 && !last) break;
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) dst[((int64_t)g * N2 + e2 + r) * rowsz] = acc[k][r][g];
+                    }
                 }
 #pragma unroll
                 for (int r = 0; r + 1 < P; ++r)
@@ -518,10 +557,11 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
         if (more) store_stage(e2 + 1);
         __syncthreads();
     }
+    if (S::DEFER) flush_row(K2 - 1);
 }
 
 template <int P, bool STIFF, typename CT, int L2M>
-__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
+__global__ __launch_bounds__((A12Shape<P, STIFF>::NT), (A12Shape<P, STIFF>::WPE)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
                                                                         CT *__restrict__ A2, int q3base, int T1r)
 {
     asm12_block<P, STIFF, CT, L2M>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
@@ -981,7 +1021,7 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
 // Persistent forms: each workgroup takes blocks it = blockIdx.x, + gridDim.x,
 // ... of the concatenated per-patch grids (every patch in one chunk).
 template <int P, bool STIFF, typename CT, int L2M>
-__global__ __launch_bounds__((A12Shape<P, STIFF>::NT)) void asm12_persistent(TaskList tl)
+__global__ __launch_bounds__((A12Shape<P, STIFF>::NT), (A12Shape<P, STIFF>::WPE)) void asm12_persistent(TaskList tl)
 {
     for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
         const int t = task_of(tl.off, tl.ntask, it);
