@@ -62,11 +62,55 @@ __device__ __forceinline__ void col_ind_row(const RowIndex &ri, int64_t nrows, i
     }
 }
 
+// Rows per wavefront of the single-patch kernel.  Lane r < CI_ROWS of a
+// wavefront works out the position and first column of row row0 + r (the
+// prefix-sum loads of all its rows are in flight together); the wavefront then
+// writes the rows one after another, taking each row's description from its
+// lane by broadcast.
+constexpr int CI_ROWS = 16;
+
 template <int P>
 __global__ void col_ind_kernel(RowIndex ri, int64_t nrows, int32_t *col_ind, int64_t col_base, int64_t nnz_base)
 {
-    col_ind_row<P>(ri, nrows, col_ind, col_base, nnz_base,
-                   blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64);
+    constexpr int W = 2 * P - 1;
+    const int lane = threadIdx.x % 64;
+    const int64_t row0 = (blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64) * CI_ROWS;
+    if (row0 >= nrows) return;                                   // uniform over the wavefront
+    int64_t start = 0, first = 0;
+    int dims = 0;                                                // l0 | l1 << 8 | l2 << 16
+    if (lane < CI_ROWS && row0 + lane < nrows) {
+        const int64_t m = row0 + lane;
+        const int m0 = (int)(m % ri.N[0]);
+        const int64_t r = m / ri.N[0];
+        const int m1 = ri.d >= 2 ? (int)(r % ri.N[1]) : 0;
+        const int m2 = ri.d >= 3 ? (int)(r / ri.N[1]) : 0;
+        const int lo0 = band_lo(m0, P), l0 = band_len(m0, P, ri.N[0]);
+        const int lo1 = ri.d >= 2 ? band_lo(m1, P) : 0, l1 = ri.d >= 2 ? band_len(m1, P, ri.N[1]) : 1;
+        const int lo2 = ri.d >= 3 ? band_lo(m2, P) : 0, l2 = ri.d >= 3 ? band_len(m2, P, ri.N[2]) : 1;
+        start = nnz_base + row_start(ri, m0, m1, m2);
+        first = col_base + lo0 + (int64_t)ri.N[0] * lo1 + (int64_t)ri.N[0] * ri.N[1] * lo2;
+        dims = l0 | (l1 << 8) | (l2 << 16);
+    }
+    const int64_t N0 = ri.N[0], N01 = (int64_t)ri.N[0] * ri.N[1];
+    const int nr = nrows - row0 < CI_ROWS ? (int)(nrows - row0) : CI_ROWS;
+    for (int k = 0; k < nr; ++k) {
+        const int64_t st = __shfl(start, k, 64), fc = __shfl(first, k, 64);
+        const int dm = __shfl(dims, k, 64);
+        const int l0 = dm & 255, l1 = (dm >> 8) & 255, l2 = dm >> 16;
+        int32_t *out = col_ind + st;
+        if (ri.d == 3 && l0 == W && l1 == W && l2 == W) {
+            for (int t = lane; t < W * W * W; t += 64) {
+                const int a = t % W, b = (t / W) % W, c = t / (W * W);
+                out[t] = (int32_t)(fc + a + N0 * b + N01 * c);
+            }
+        } else {
+            const int len = l0 * l1 * l2;
+            for (int t = lane; t < len; t += 64) {
+                const int a = t % l0, b = (t / l0) % l1, c = t / (l0 * l1);
+                out[t] = (int32_t)(fc + a + N0 * b + N01 * c);
+            }
+        }
+    }
 }
 
 // Persistent forms over the rows of a batch: block bx of a task covers rows
@@ -140,7 +184,8 @@ hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_in
                            nnz_base);
     }
     if (col_ind) {
-        int64_t nb = (pv.N + 3) / 4;
+        const int64_t per_block = 4 * CI_ROWS;                   // 4 wavefronts of CI_ROWS rows
+        int64_t nb = (pv.N + per_block - 1) / per_block;
         dim3 g((unsigned)nb), b(256);
         switch (pv.P) {
         case 2: hipLaunchKernelGGL(col_ind_kernel<2>, g, b, 0, s, pv.ri, pv.N, col_ind, col_base, nnz_base); break;
