@@ -1069,13 +1069,18 @@ static hipError_t launch_asm3_batch_t(const TaskList &tl, int nblocks, hipStream
     return hipGetLastError();
 }
 
+// Level 2 in FP64: on the matrix cores where the full slot tiles win (p = 4,
+// 8), on the vector ALU over the stored windows only for the other orders
+// (FP64 matrix cores and vector FMA have the same peak on this chip).
+template <int P> constexpr int f64_level2() { return (P == 4 || P == 8) ? 1 : 0; }
+
 template <int P>
 static hipError_t launch_batch_p(int which, const TaskList &tl, int op, Prec prec, int nblocks, hipStream_t s)
 {
     if (which == 0) {
         if (prec == Prec::F64)
-            return op == 2 ? launch_asm12_batch_t<P, true, double, 1>(tl, nblocks, s)
-                           : launch_asm12_batch_t<P, false, double, 1>(tl, nblocks, s);
+            return op == 2 ? launch_asm12_batch_t<P, true, double, f64_level2<P>()>(tl, nblocks, s)
+                           : launch_asm12_batch_t<P, false, double, f64_level2<P>()>(tl, nblocks, s);
         if (prec == Prec::BF16X3)
             return op == 2 ? launch_asm12_batch_t<P, true, float, 2>(tl, nblocks, s)
                            : launch_asm12_batch_t<P, false, float, 2>(tl, nblocks, s);
@@ -1143,7 +1148,7 @@ template <int P>
 static hipError_t launch_asm_p(const PatchView &pv, int op, Prec prec, const void *C, double *vals, void *ws,
                                size_t ws_bytes, hipStream_t s, int t1, int seg)
 {
-    if (prec == Prec::F64) return launch_asm_pt<P, double, 1>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
+    if (prec == Prec::F64) return launch_asm_pt<P, double, f64_level2<P>()>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
     if (prec == Prec::BF16X3) return launch_asm_pt<P, float, 2>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
     return launch_asm_pt<P, float, 0>(pv, op, C, vals, ws, ws_bytes, s, t1, seg);
 }
