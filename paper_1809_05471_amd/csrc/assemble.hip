@@ -17,14 +17,15 @@
 //    the (i, j) pairs (vector ALU; (2, 1) equals (1, 2) at this level).
 //    Level 2 then adds the element's p points x2: pairs that share their
 //    direction-3 tables are summed here (Sec. 3.1 splitting: 4 groups BB,
-//    BD, DB, DD for the stiffness).  In FP64 it runs on the matrix cores
-//    (rows = slots (m2 mod p, n2 mod p), columns = (m1, n1), K = (pair, x2));
-//    in BF16 split on bf16 matrix cores with hi/lo operands; in FP32 on the
-//    vector ALU with a sliding window of the p rows m2.  Both operators are
-//    symmetric, so only the entries with n2 > m2, or n2 == m2 and n1 >= m1,
-//    are kept (the partial of group (a, b) at (n12, m12) is that of (b, a)
-//    at (m12, n12)): ((p - 1)(2p - 1) + p of the (2p - 1)^2 windows).  A
-//    kept entry is written to the level-2 partial of its plane,
+//    BD, DB, DD for the stiffness).  In FP64 at p = 4 and 8 it runs on the
+//    matrix cores (rows = slots (m2 mod p, n2 mod p), columns = (m1, n1),
+//    K = (pair, x2)); in BF16 split on bf16 matrix cores with hi/lo operands;
+//    in FP32, and in FP64 at the other orders, on the vector ALU with a
+//    sliding window of the p rows m2 over the stored entries only.  Both
+//    operators are symmetric, so only the entries with n2 > m2, or n2 == m2
+//    and n1 >= m1, are kept (the partial of group (a, b) at (n12, m12) is
+//    that of (b, a) at (m12, n12)): ((p - 1)(2p - 1) + p of the (2p - 1)^2
+//    windows).  A kept entry is written to the level-2 partial of its plane,
 //      A2[g][m2][m1][kh(n1 - m1 + p - 1, n2 - m2 + p - 1)],
 //    once its last element e2 has been added.
 //
