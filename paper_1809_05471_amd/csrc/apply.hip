@@ -69,8 +69,13 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     // the pointwise stage, which keeps the registers low enough for more
     // resident waves (measured faster from order 3 on)
     constexpr bool PRE = P * NC <= 12;
-    constexpr int NCR = PRE ? P : 1;
-    CT cur[NCR][NC], nxt[NCR][NC];
+    // FP64 at order 4: the LDS already limits the kernel to 3 waves per SIMD,
+    // so the current layer's coefficients fit in registers at no cost;
+    // they are loaded at the start of the layer and have the two forward
+    // stages to arrive
+    constexpr bool LAYER = !PRE && sizeof(CT) == sizeof(double) && P == 4;
+    constexpr int NCR = (PRE || LAYER) ? P : 1;
+    CT cur[NCR][NC], nxt[PRE ? NCR : 1][NC];
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
     auto load_plane = [&](int e3, int g3, CT *dst) {
 #pragma unroll
@@ -121,6 +126,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
             t3D[i] = (CT)d2.D[(int64_t)e3 * PP + i];
         }
         if (PRE && e3 < e3z) load_layer(e3 + 1, nxt);
+        if (LAYER) load_layer(e3, cur);
         __syncthreads();
         // ---- forward, direction 3: a = B3 x, b = D3 x, every plane
         for (int idx = tid; idx < P * NXY; idx += NT) {
@@ -161,11 +167,11 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         // ---- forward, direction 1, and the pointwise coefficient, every plane
         if (tid < TX * TY) {
             const CT *b1 = t1B + (le1 * P + g1) * P, *db1 = t1D + (le1 * P + g1) * P;
-#pragma unroll (PRE ? P : 1)
+#pragma unroll ((PRE || LAYER) ? P : 1)
             for (int g3 = 0; g3 < P; ++g3) {
                 CT cpl[NC];
-                if (!PRE) load_plane(e3, g3, cpl);
-                const CT *cg = PRE ? cur[g3 < NCR ? g3 : 0] : cpl;
+                if (!PRE && !LAYER) load_plane(e3, g3, cpl);
+                const CT *cg = (PRE || LAYER) ? cur[g3 < NCR ? g3 : 0] : cpl;
                 CT h[NF];
                 if (STIFF) {
                     CT gr0 = CT(0), gr1 = CT(0), gr2 = CT(0);
@@ -258,7 +264,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
 #pragma unroll
             for (int g3 = 0; g3 < P; ++g3)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) cur[g3 < NCR ? g3 : 0][c] = nxt[g3 < NCR ? g3 : 0][c];
+                for (int c = 0; c < NC; ++c) cur[g3 < NCR ? g3 : 0][c] = nxt[PRE && g3 < NCR ? g3 : 0][c];
         }
     }
     __syncthreads();
