@@ -82,7 +82,9 @@ __device__ __forceinline__ double eval_coef(const Coef &c, const double *x, int 
     if (c.kind == 0) return c.value;
     if (c.kind == 2) return c.qp[qlin];
     double s = 1.0;
-    for (int i = 0; i < d; ++i) s *= sin(2.0 * 3.14159265358979323846 * x[i]);
+    // sin(2 pi x) as sinpi(2 x): the argument reduction is exact in FP64 and
+    // cheaper than reducing a multiple of pi
+    for (int i = 0; i < d; ++i) s *= sinpi(2.0 * x[i]);
     return 1.0 + c.value * s;
 }
 
