@@ -164,6 +164,20 @@ sf_status sf_patch_quad_points(sf_patch *patch, double *dev_xyz);
  * operator at a precision; repeating it is allowed (recomputes). */
 sf_status sf_patch_prepare(sf_patch *patch, unsigned ops, sf_precision prec);
 
+/* sf_patch_prepare without the synchronisation (Sec. 6.3, as above): queues
+ * the geometry kernel on the patch's stream and returns; the operators count
+ * as prepared at once, so assemble/apply may follow on the same stream.  The
+ * det J <= 0 test is still made at every quadrature point; its outcome stays
+ * on the device and accumulates over calls until sf_patch_geometry_check
+ * reports it (sf_patch_prepare clears it).  Argument errors are returned as
+ * by sf_patch_prepare; a det J failure is not. */
+sf_status sf_patch_prepare_async(sf_patch *patch, unsigned ops, sf_precision prec);
+
+/* Outcome of the det J test of every sf_patch_prepare_async since the last
+ * check: SF_OK, or SF_EGEOM if det J <= 0 was seen anywhere.  Synchronises
+ * the patch's stream and clears the recorded outcome. */
+sf_status sf_patch_geometry_check(sf_patch *patch);
+
 /* Structural CSR pattern (Sec. 3.2): dev_row_ptr [N+1] int64 and
  * dev_col_ind [nnz] int32, device.  Requires N < 2^31.  Asynchronous. */
 sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col_ind);

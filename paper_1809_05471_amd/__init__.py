@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4:
 EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target", "sf_host_tables_1d",
             "sf_patch_create",
             "sf_patch_info", "sf_patch_set_coef", "sf_patch_quad_points", "sf_patch_prepare",
-            "sf_csr_pattern", "sf_assemble", "sf_apply", "sf_patch_destroy", "sf_batch_create",
+            "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_apply", "sf_patch_destroy", "sf_batch_create",
             "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_batch_destroy"]
 
 
@@ -63,6 +63,8 @@ def lib():
         "sf_patch_set_coef": (st, [vp, ctypes.c_uint, ctypes.c_int, vp]),
         "sf_patch_quad_points": (st, [vp, vp]),
         "sf_patch_prepare": (st, [vp, ctypes.c_uint, ctypes.c_int]),
+        "sf_patch_prepare_async": (st, [vp, ctypes.c_uint, ctypes.c_int]),
+        "sf_patch_geometry_check": (st, [vp]),
         "sf_csr_pattern": (st, [vp, vp, vp]),
         "sf_assemble": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
         "sf_apply": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
@@ -183,6 +185,14 @@ def sf_patch_quad_points(ctx, patch, xyz):
 
 def sf_patch_prepare(ctx, patch, ops, prec=SF_FP64):
     _check(lib().sf_patch_prepare(patch, ops, prec), ctx)
+
+
+def sf_patch_prepare_async(ctx, patch, ops, prec=SF_FP64):
+    _check(lib().sf_patch_prepare_async(patch, ops, prec), ctx)
+
+
+def sf_patch_geometry_check(ctx, patch):
+    _check(lib().sf_patch_geometry_check(patch), ctx)
 
 
 def sf_csr_pattern(ctx, patch, row_ptr, col_ind):

@@ -251,6 +251,7 @@ sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out
         }
     }
     if (e == hipSuccess) e = hipMalloc((void **)&p->dflag, sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(p->dflag, 0, sizeof(int), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         free_patch_memory(p);
@@ -308,7 +309,10 @@ sf_status sf_patch_quad_points(sf_patch *p, double *dev_xyz)
     return SF_OK;
 }
 
-sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
+// Geometry step.  sync: clear the det J flag, run, read the flag back and
+// report it.  Otherwise only the kernel is queued; the flag keeps any det J <= 0
+// seen since the last sf_patch_geometry_check, which reads and clears it.
+static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool sync)
 {
     if (!p) return SF_EINVAL;
     sf_ctx *ctx = p->ctx;
@@ -343,17 +347,44 @@ sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
             if (cidx(m) == ci) p->ready[oi][m] = false;
         if (oi == 0) o.c_mass = p->C[oi][ci]; else o.c_stiff = p->C[oi][ci];
     }
-    hipError_t e = hipMemsetAsync(p->dflag, 0, sizeof(int), s);
+    hipError_t e = sync ? hipMemsetAsync(p->dflag, 0, sizeof(int), s) : hipSuccess;
     if (e == hipSuccess) e = launch_geometry(p->view, o, s);
     int flag = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (sync) {
+        if (e == hipSuccess) e = hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "geometry step");
     if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
     for (int oi = 0; oi < 2; ++oi)
         if (ops & (oi == 0 ? SF_MASS : SF_STIFF))
             for (int m = 0; m < 3; ++m)
                 if (cidx(m) == ci) p->ready[oi][m] = true;     // FP32 storage serves FP32 and BF16 split
+    return SF_OK;
+}
+
+sf_status sf_patch_prepare(sf_patch *p, unsigned ops, sf_precision prec)
+{
+    return prepare_impl(p, ops, prec, true);
+}
+
+sf_status sf_patch_prepare_async(sf_patch *p, unsigned ops, sf_precision prec)
+{
+    return prepare_impl(p, ops, prec, false);
+}
+
+sf_status sf_patch_geometry_check(sf_patch *p)
+{
+    if (!p) return SF_EINVAL;
+    sf_ctx *ctx = p->ctx;
+    ctx->err.clear();
+    hipStream_t s = ctx->stream;
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->dflag, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "geometry check");
+    if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
     return SF_OK;
 }
 

@@ -397,6 +397,32 @@ def test_batched_equals_single_patch():
                 g.close()
 
 
+def test_async_prepare_and_geometry_check():
+    """sf_patch_prepare_async queues the same geometry kernel as
+    sf_patch_prepare: the stiffness assembled after it is bitwise the same.
+    A folded map's det J failure is not returned by the call but by
+    sf_patch_geometry_check, which clears it (the next check passes)."""
+    import torch
+    w = inputs.workload_3d((6, 5, 7), 3)
+    with GpuPatch(w["knots"], 3, w["ctrl"], coef=("sinprod", 0.5)) as g:
+        g.prepare(sf.SF_STIFF)
+        a_sync = g.assemble(sf.SF_STIFF)
+        sf.sf_patch_prepare_async(g.ctx, g.h, sf.SF_STIFF, sf.SF_FP64)
+        a_async = g.assemble(sf.SF_STIFF)
+        sf.sf_patch_geometry_check(g.ctx, g.h)
+        assert np.array_equal(a_sync.view(np.int64), a_async.view(np.int64))
+    kn, ctrl = inputs.identity_geometry((3, 3, 3), 3)
+    folded = ctrl.copy()
+    folded[:, 0] = -folded[:, 0]                    # mirrored map: det J < 0 everywhere
+    with GpuPatch(kn, 3, folded) as g:
+        sf.sf_patch_prepare_async(g.ctx, g.h, sf.SF_STIFF, sf.SF_FP64)   # no error here
+        with pytest.raises(sf.SfError) as e:
+            sf.sf_patch_geometry_check(g.ctx, g.h)
+        assert e.value.status == sf.SF_EGEOM
+        sf.sf_patch_geometry_check(g.ctx, g.h)       # cleared by the check
+    torch.cuda.synchronize()
+
+
 def test_error_paths():
     kn, ctrl = inputs.identity_geometry((3, 3, 3), 3)
     folded = ctrl.copy()
