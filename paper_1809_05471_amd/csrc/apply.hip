@@ -69,11 +69,12 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     // the pointwise stage, which keeps the registers low enough for more
     // resident waves (measured faster from order 3 on)
     constexpr bool PRE = P * NC <= 12;
-    // FP64 at order 4: the LDS already limits the kernel to 3 waves per SIMD,
-    // so the current layer's coefficients fit in registers at no cost;
-    // they are loaded at the start of the layer and have the two forward
-    // stages to arrive
-    constexpr bool LAYER = !PRE && sizeof(CT) == sizeof(double) && P == 4;
+    // FP64 at order 4 and FP32 at order 3: the current layer's coefficients
+    // are held in registers at little or no cost in occupancy (at FP64 order
+    // 4 the LDS already limits the kernel to 3 waves per SIMD); they are
+    // loaded at the start of the layer and have the two forward stages to
+    // arrive.  Measured slower for the other orders.
+    constexpr bool LAYER = !PRE && (sizeof(CT) == sizeof(double) ? P == 4 : P == 3);
     constexpr int NCR = (PRE || LAYER) ? P : 1;
     CT cur[NCR][NC], nxt[PRE ? NCR : 1][NC];
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
