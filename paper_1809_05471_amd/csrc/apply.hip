@@ -9,7 +9,7 @@
 // sense of Sec. 4 - with one thread per quadrature column (q1, q2).  The
 // workgroup walks its layers in order with sliding windows of the p rows of x
 // and of partial y that the current layer touches; every stage handles all
-// p quadrature planes of the layer at once (5 barriers per layer).  The
+// p quadrature planes of the layer at once (6 barriers per layer).  The
 // coefficient tensor is the only stream that scales with Q; it is read plane
 // by plane in the pointwise stage (prefetched a layer ahead only where that
 // costs no occupancy).  LZ is tuned per patch by the caller.  Partial y rows
@@ -224,31 +224,41 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
             for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
         }
         __syncthreads();
-        // ---- backward, direction 2, then direction 3 into the y window
+        // ---- backward, direction 2: one item per (plane, function column), into
+        // sq (the pointwise results in sa are dead once direction 1 has run)
+        CT *sq = sa;                                 // [2][P][NY][NX]
+        for (int idx = tid; idx < P * NXY; idx += NT) {
+            const int j2 = idx % NXY, g3 = idx / NXY;
+            const int lx = j2 % NX, ly = j2 / NX;
+            CT sB = CT(0), sD = CT(0);
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const int l2 = ly - j;
+                if (l2 < 0 || l2 >= E) continue;
+#pragma unroll
+                for (int h2 = 0; h2 < P; ++h2) {
+                    const CT bv = t2B[(l2 * P + h2) * P + j];
+                    const int row = (g3 * TY + l2 * P + h2) * NX + lx;
+                    if (STIFF) {
+                        sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
+                        sD += bv * sr[2 * P * TY * NX + row];
+                    } else {
+                        sB += bv * sr[row];
+                    }
+                }
+            }
+            sq[g3 * NXY + j2] = sB;
+            if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+        }
+        __syncthreads();
+        // ---- backward, direction 3 into the y window
         for (int idx = tid; idx < NXY; idx += NT) {
-            const int lx = idx % NX, ly = idx / NX;
             CT acc[P];
 #pragma unroll
             for (int s = 0; s < P; ++s) acc[s] = CT(0);
-#pragma unroll 1
+#pragma unroll
             for (int g3 = 0; g3 < P; ++g3) {
-                CT sB = CT(0), sD = CT(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l2 = ly - j;
-                    if (l2 < 0 || l2 >= E) continue;
-#pragma unroll
-                    for (int h2 = 0; h2 < P; ++h2) {
-                        const CT bv = t2B[(l2 * P + h2) * P + j];
-                        const int row = (g3 * TY + l2 * P + h2) * NX + lx;
-                        if (STIFF) {
-                            sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
-                            sD += bv * sr[2 * P * TY * NX + row];
-                        } else {
-                            sB += bv * sr[row];
-                        }
-                    }
-                }
+                const CT sB = sq[g3 * NXY + idx], sD = STIFF ? sq[(P + g3) * NXY + idx] : CT(0);
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
                     acc[s] += t3B[g3 * P + s] * sB;
