@@ -9,7 +9,7 @@
 // sense of Sec. 4 - with one thread per quadrature column (q1, q2).  The
 // workgroup walks its layers in order with sliding windows of the p rows of x
 // and of partial y that the current layer touches; every stage handles all
-// p quadrature planes of the layer at once (6 barriers per layer).  The
+// p quadrature planes of the layer at once (6 or 7 barriers per layer).  The
 // coefficient tensor is the only stream that scales with Q; it is read plane
 // by plane in the pointwise stage (prefetched a layer ahead only where that
 // costs no occupancy).  LZ is tuned per patch by the caller.  Partial y rows
@@ -75,6 +75,9 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     // loaded at the start of the layer and have the two forward stages to
     // arrive.  Measured slower for the other orders.
     constexpr bool LAYER = !PRE && (sizeof(CT) == sizeof(double) ? P == 4 : P == 3);
+    // Backward direction 1 in two steps (per-element sums, then per-column
+    // sums) where it pays: FP64 from order 3, FP32 from order 5 (measured).
+    constexpr bool TWOSTEP = sizeof(CT) == sizeof(double) ? P >= 3 : P >= 5;
     constexpr int NCR = (PRE || LAYER) ? P : 1;
     CT cur[NCR][NC], nxt[PRE ? NCR : 1][NC];
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
@@ -198,32 +201,79 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         }
         __syncthreads();
         // ---- backward, direction 1: D1^T h1, B1^T h2, B1^T h3 (mass: B1^T h)
-        for (int idx = tid; idx < P * TY * NX; idx += NT) {
-            const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
-            CT r[NF];
+        if constexpr (TWOSTEP) {
+            // In two steps in place over sh.  First, per (plane, row, element l1), the
+            // p sums over the element's points, part[f][j] = sum_h T_f(l1, h, j)
+            // v[f][h], written over the element's own p values; then, per function
+            // column lx, the sum over the <= p elements that share it.
+            for (int idx = tid; idx < P * TY * E; idx += NT) {
+                const int l1 = idx % E, rest = idx / E;
+                const int yy = rest % TY, g3 = rest / TY;
+                const int col0 = (g3 * TY + yy) * TX + l1 * P;
+                CT v[NF][P];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) r[f] = CT(0);
+                for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int l1 = lx - j;                    // element whose local function j is lx
-                if (l1 < 0 || l1 >= E) continue;
+                    for (int h = 0; h < P; ++h) v[f][h] = sh[f * P * TY * TX + col0 + h];
 #pragma unroll
-                for (int h1 = 0; h1 < P; ++h1) {
-                    const CT bv = t1B[(l1 * P + h1) * P + j];
-                    const int col = (g3 * TY + yy) * TX + l1 * P + h1;
-                    if (STIFF) {
-                        r[0] += t1D[(l1 * P + h1) * P + j] * sh[0 * P * TY * TX + col];
-                        r[NF > 1 ? 1 : 0] += bv * sh[1 * P * TY * TX + col];
-                        r[NF > 2 ? 2 : 0] += bv * sh[2 * P * TY * TX + col];
-                    } else {
-                        r[0] += bv * sh[col];
+                for (int f = 0; f < NF; ++f) {
+                    const CT *T = (STIFF && f == 0) ? t1D : t1B;
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        CT part = CT(0);
+#pragma unroll
+                        for (int h = 0; h < P; ++h) part += T[(l1 * P + h) * P + j] * v[f][h];
+                        sh[f * P * TY * TX + col0 + j] = part;
                     }
                 }
             }
+            __syncthreads();
+            for (int idx = tid; idx < P * TY * NX; idx += NT) {
+                const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
+                CT r[NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
+                for (int f = 0; f < NF; ++f) r[f] = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l1 = lx - j;                    // element whose local function j is lx
+                    if (l1 < 0 || l1 >= E) continue;
+                    const int col = (g3 * TY + yy) * TX + l1 * P + j;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) r[f] += sh[f * P * TY * TX + col];
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
+            }
+            __syncthreads();
+        } else {
+            // one item per (plane, row, function column), p^2 terms each
+            for (int idx = tid; idx < P * TY * NX; idx += NT) {
+                const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
+                CT r[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) r[f] = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l1 = lx - j;                    // element whose local function j is lx
+                    if (l1 < 0 || l1 >= E) continue;
+#pragma unroll
+                    for (int h1 = 0; h1 < P; ++h1) {
+                        const CT bv = t1B[(l1 * P + h1) * P + j];
+                        const int col = (g3 * TY + yy) * TX + l1 * P + h1;
+                        if (STIFF) {
+                            r[0] += t1D[(l1 * P + h1) * P + j] * sh[0 * P * TY * TX + col];
+                            r[NF > 1 ? 1 : 0] += bv * sh[1 * P * TY * TX + col];
+                            r[NF > 2 ? 2 : 0] += bv * sh[2 * P * TY * TX + col];
+                        } else {
+                            r[0] += bv * sh[col];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // ---- backward, direction 2: one item per (plane, function column), into
         // sq (the pointwise results in sa are dead once direction 1 has run)
         CT *sq = sa;                                 // [2][P][NY][NX]
