@@ -9,7 +9,7 @@
 // sense of Sec. 4 - with one thread per quadrature column (q1, q2).  The
 // workgroup walks its layers in order with sliding windows of the p rows of x
 // and of partial y that the current layer touches; every stage handles all
-// p quadrature planes of the layer at once (6 or 7 barriers per layer).  The
+// p quadrature planes of the layer at once (6 to 8 barriers per layer).  The
 // coefficient tensor is the only stream that scales with Q; it is read plane
 // by plane in the pointwise stage (prefetched a layer ahead only where that
 // costs no occupancy).  LZ is tuned per patch by the caller.  Partial y rows
@@ -75,8 +75,9 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     // loaded at the start of the layer and have the two forward stages to
     // arrive.  Measured slower for the other orders.
     constexpr bool LAYER = !PRE && (sizeof(CT) == sizeof(double) ? P == 4 : P == 3);
-    // Backward direction 1 in two steps (per-element sums, then per-column
-    // sums) where it pays: FP64 from order 3, FP32 from order 5 (measured).
+    // Backward directions 1 and 2 in two steps (per-element sums, then sums
+    // over the elements sharing a function) where it pays: FP64 from order 3,
+    // FP32 from order 5 (measured).
     constexpr bool TWOSTEP = sizeof(CT) == sizeof(double) ? P >= 3 : P >= 5;
     constexpr int NCR = (PRE || LAYER) ? P : 1;
     CT cur[NCR][NC], nxt[PRE ? NCR : 1][NC];
@@ -274,33 +275,84 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
             }
             __syncthreads();
         }
-        // ---- backward, direction 2: one item per (plane, function column), into
-        // sq (the pointwise results in sa are dead once direction 1 has run)
+        // ---- backward, direction 2 into sq (the pointwise results in sa are
+        // dead once direction 1 has run)
         CT *sq = sa;                                 // [2][P][NY][NX]
-        for (int idx = tid; idx < P * NXY; idx += NT) {
-            const int j2 = idx % NXY, g3 = idx / NXY;
-            const int lx = j2 % NX, ly = j2 / NX;
-            CT sB = CT(0), sD = CT(0);
+        if constexpr (TWOSTEP) {
+            // In two steps, in place over sr: per (plane, element l2, column lx)
+            // the p sums over the element's points (sB into field 0, sD into
+            // field 1 of the element's own rows), then per function row the sum
+            // over the <= p elements that share it.
+            for (int idx = tid; idx < P * E * NX; idx += NT) {
+                const int lx = idx % NX, rest = idx / NX;
+                const int l2 = rest % E, g3 = rest / E;
+                const int row0 = (g3 * TY + l2 * P) * NX + lx;          // point h: row0 + h NX
+                CT v[NF][P];
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int l2 = ly - j;
-                if (l2 < 0 || l2 >= E) continue;
+                for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int h2 = 0; h2 < P; ++h2) {
-                    const CT bv = t2B[(l2 * P + h2) * P + j];
-                    const int row = (g3 * TY + l2 * P + h2) * NX + lx;
-                    if (STIFF) {
-                        sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
-                        sD += bv * sr[2 * P * TY * NX + row];
-                    } else {
-                        sB += bv * sr[row];
+                    for (int h = 0; h < P; ++h) v[f][h] = sr[f * P * TY * NX + row0 + h * NX];
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    CT pB = CT(0), pD = CT(0);
+#pragma unroll
+                    for (int h = 0; h < P; ++h) {
+                        const CT bv = t2B[(l2 * P + h) * P + j];
+                        if (STIFF) {
+                            pB += bv * v[0][h] + t2D[(l2 * P + h) * P + j] * v[NF > 1 ? 1 : 0][h];
+                            pD += bv * v[NF > 2 ? 2 : 0][h];
+                        } else {
+                            pB += bv * v[0][h];
+                        }
                     }
+                    sr[row0 + j * NX] = pB;
+                    if (STIFF) sr[1 * P * TY * NX + row0 + j * NX] = pD;
                 }
             }
-            sq[g3 * NXY + j2] = sB;
-            if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+            __syncthreads();
+            for (int idx = tid; idx < P * NXY; idx += NT) {
+                const int j2 = idx % NXY, g3 = idx / NXY;
+                const int lx = j2 % NX, ly = j2 / NX;
+                CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l2 = ly - j;
+                    if (l2 < 0 || l2 >= E) continue;
+                    const int row = (g3 * TY + l2 * P + j) * NX + lx;
+                    sB += sr[row];
+                    if (STIFF) sD += sr[1 * P * TY * NX + row];
+                }
+                sq[g3 * NXY + j2] = sB;
+                if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+            }
+            __syncthreads();
+        } else {
+            // one item per (plane, function column), p^2 terms each
+            for (int idx = tid; idx < P * NXY; idx += NT) {
+                const int j2 = idx % NXY, g3 = idx / NXY;
+                const int lx = j2 % NX, ly = j2 / NX;
+                CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l2 = ly - j;
+                    if (l2 < 0 || l2 >= E) continue;
+#pragma unroll
+                    for (int h2 = 0; h2 < P; ++h2) {
+                        const CT bv = t2B[(l2 * P + h2) * P + j];
+                        const int row = (g3 * TY + l2 * P + h2) * NX + lx;
+                        if (STIFF) {
+                            sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
+                            sD += bv * sr[2 * P * TY * NX + row];
+                        } else {
+                            sB += bv * sr[row];
+                        }
+                    }
+                }
+                sq[g3 * NXY + j2] = sB;
+                if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // ---- backward, direction 3 into the y window
         for (int idx = tid; idx < NXY; idx += NT) {
             CT acc[P];
