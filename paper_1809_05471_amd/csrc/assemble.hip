@@ -194,7 +194,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     constexpr int NH = S::NH;
     constexpr int NP1 = STIFF ? 8 : 1;                  // pairs formed at level 1
     // x2 points per level-1 lane (a divisor of p, bounded by registers)
-    constexpr int G2B = (P == 2 || P == 6 || P == 8) ? 2 : 1;
+    constexpr int G2B = (P == 2 || P == 6 || P == 8 || (P == 4 && sizeof(CT) == sizeof(float))) ? 2 : 1;
     constexpr int NGB = P / G2B;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *cs = reinterpret_cast<CT *>(smem_raw);          // [NCOMP][g2][g1][XE]
