@@ -70,6 +70,34 @@ def test_3d_full_parity_several_tiles(K, p):
     _full_parity(kn, p, ctrl, ("sinprod", 0.5))
 
 
+def _random_shapes(n, seed, budget=1.2e9):
+    """Seeded random ragged 3D shapes: 1..10 elements per direction, orders
+    2..7, with the oracle's cost (elements x p^9) under `budget`."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        p = int(rng.integers(2, 8))
+        K = tuple(int(k) for k in rng.integers(1, 11, size=3))
+        if np.prod(K) * float(p) ** 9 <= budget:
+            out.append((K, p))
+    return out
+
+
+@pytest.mark.parametrize("K,p", _random_shapes(10, seed=2024))
+def test_3d_random_shapes(K, p):
+    """Random ragged shapes: single elements, fewer elements than p, row
+    tiles and level-2 windows cut at the mesh edges in every combination the
+    draw produces; full matrices and products against the oracle."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=7)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5))
+
+
+@pytest.mark.parametrize("K,p", _random_shapes(6, seed=77))
+def test_3d_random_shapes_fp32(K, p):
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=8)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP32, tol=TOL32)
+
+
 @pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((3, 4, 3), 4), ((2, 3, 2), 6)])
 def test_3d_fp32_mode(K, p):
     kn, ctrl = inputs.perturbed_geometry(K, p, seed=4)
