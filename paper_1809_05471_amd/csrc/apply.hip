@@ -172,7 +172,8 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         // ---- forward, direction 1, and the pointwise coefficient, every plane
         if (tid < TX * TY) {
             const CT *b1 = t1B + (le1 * P + g1) * P, *db1 = t1D + (le1 * P + g1) * P;
-#pragma unroll ((PRE || LAYER) ? P : 1)
+            constexpr int UNR = (PRE || LAYER) ? P : 1;   // planes unrolled (registers hold cur)
+#pragma unroll UNR
             for (int g3 = 0; g3 < P; ++g3) {
                 CT cpl[NC];
                 if (!PRE && !LAYER) load_plane(e3, g3, cpl);
