@@ -108,7 +108,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the sharding design is described in the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
