@@ -150,8 +150,7 @@ struct A12Shape {
     static constexpr bool DEFER = P <= 4;
     static constexpr int XE = T1 + P - 1;        // direction-1 elements touching the tile
     static constexpr int NSLICE = NCOMP * P * P * XE;        // coefficient slice of one element e2
-    static constexpr int NSTAGE = NSLICE + 2 * P * P;        // + its direction-2 tables
-    static constexpr int PF = (NSTAGE + NT - 1) / NT;        // staged values per thread
+    static constexpr int PF = (NSLICE + NT - 1) / NT;        // staged slice values per thread
     static constexpr int ITEMS = (T1 * NH + NT - 1) / NT;     // level-2 entries per thread
     static constexpr int L1SZ = P * NP * T1 * W;             // level-1 results of one element
     // level 2 on the matrix cores (FP64): slots (m2 mod p, n2 mod p) as rows,
@@ -193,6 +192,9 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
     constexpr int NH = S::NH;
     constexpr int NP1 = STIFF ? 8 : 1;                  // pairs formed at level 1
+    // the next element's stage loads are issued before level 1 instead of
+    // after it (measured faster at p = 2 and for the FP32-stored tiles at p = 4)
+    constexpr bool EARLY = P == 2 || (P == 4 && sizeof(CT) == sizeof(float));
     // x2 points per level-1 lane (a divisor of p, bounded by registers)
     constexpr int G2B = (P == 2 || P == 6 || P == 8 || (P == 4 && sizeof(CT) == sizeof(float))) ? 2 : 1;
     constexpr int NGB = P / G2B;
@@ -230,14 +232,14 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
         t1D[i] = ok ? d0.D[(int64_t)e1 * P * P + gj] : 0.0;
     }
 
-    // staged values of one element e2: coefficient slice (global order comp,
-    // g2, x1 with x1 fastest) followed by the element's direction-2 tables.
+    // staged values of one element e2: the coefficient slice (global order
+    // comp, g2, x1 with x1 fastest) and the element's direction-2 tables.
     // The loaded values are not touched until they are stored to LDS (masking
     // included): an instruction that reads a load's result waits for it, and
     // for every memory operation issued before it, the A2 stores among them.
     static_assert(2 * P * P <= NT, "at most one table value per thread");
     CT sv[S::PF];              // coefficient slice values as loaded
-    double tv = 0.0;           // this thread's table value
+    double tv = 0.0;           // table value of the first 2p^2 threads
     auto load_stage = [&](int e2) {
         const CT *base = C + (int64_t)q3 * NCOMP * Q1 * Q0;
 #pragma unroll
@@ -249,11 +251,18 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int q0 = eb1 * P + lq1, q1 = e2 * P + g2;
                 const bool ok = q0 >= 0 && q0 < Q0;
                 sv[k] = base[ok ? ((int64_t)comp * Q1 + q1) * Q0 + q0 : 0];
-            } else if (idx < S::NSTAGE) {
-                const int t = idx - S::NSLICE;
-                const int which = t / (P * P), gj = t % (P * P);
-                tv = (which ? d1.D : d1.B)[(int64_t)e2 * P * P + gj];
             }
+        }
+        if (tid < 2 * P * P) {
+            // a register of its own: a table value sharing one with the slice
+            // values of other lanes made the compiler wait for those loads
+            // before issuing this one
+            int t = tid;
+            // opaque here, so that the table address is formed from the scalar
+            // bases at each call instead of being kept (or spilled) in vector
+            // registers across the element loop
+            asm volatile("" : "+v"(t));
+            tv = (t < P * P ? d1.B : d1.D)[e2 * P * P + t % (P * P)];
         }
     };
     auto store_stage = [&](int e2) {
@@ -266,10 +275,9 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int le1 = lq1 / P, g1 = lq1 % P;
                 const int q0 = eb1 * P + lq1;
                 cs[(r * P + g1) * XE + le1] = (q0 >= 0 && q0 < Q0) ? sv[k] : CT(0);
-            } else if (idx < S::NSTAGE) {
-                t2[idx - S::NSLICE] = tv;
             }
         }
+        if (tid < 2 * P * P) t2[tid] = tv;
     };
 
     static_assert(L2M != 1 || sizeof(CT) == sizeof(double), "FP64 matrix cores take FP64 operands");
@@ -313,11 +321,17 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     __syncthreads();
 
     // per element: level 1 | barrier | level 2 while the next slice is stored
-    // (level 2 reads no slice, and the tables are double-buffered) | barrier
+    // (level 2 reads no slice, and the tables are double-buffered) | barrier.
+    // The stage of the next element is loaded and stored on every pass (the
+    // last element reloads itself): with a condition around them, the
+    // compiler's count of loads in flight is lost at the loop's back edge and
+    // it waits for every earlier memory operation before the next loads.
     for (int e2 = 0; e2 < K2; ++e2) {
         t2B = t2buf + (e2 & 1) * 2 * P * P;
         t2D = t2B + P * P;
         if (S::DEFER && e2 > 0) flush_row(e2 - 1);
+        const int en = e2 + 1 < K2 ? e2 + 1 : e2;
+        if constexpr (EARLY) load_stage(en);
         // ---------------- level 1: contract x1 for every row of the tile.
         // One lane per (pair, row m1) forms all p x2 points of the element, so
         // the table values of each (element, x1 point) serve p x2 points.
@@ -363,8 +377,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 for (int c = 0; c < W; ++c) l1[(((gb * G2B + g) * NP + pair) * T1 + lm1) * W + c] = a[g][c];
         }
         __syncthreads();
-        const bool more = e2 + 1 < K2;
-        if (more) load_stage(e2 + 1);
+        if constexpr (!EARLY) load_stage(en);
 
         // ---------------- level 2: fold x2 into the rows m2 = e2 + r
         const bool last = e2 == K2 - 1;
@@ -555,7 +568,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 for (int g = 0; g < NG; ++g) acc[k][P - 1][g] = CT(0);
             }
         }
-        if (more) store_stage(e2 + 1);
+        store_stage(e2 + 1);   // into table buffer (e2 + 1) & 1, not the one level 2 reads
         __syncthreads();
     }
     if (S::DEFER) flush_row(K2 - 1);
