@@ -53,13 +53,17 @@ namespace sfiga {
 
 template <int P> struct A12Cfg;                // threads per workgroup, max rows m1 per tile
 // (T1 (2p - 1) columns fill the waves' 16-column blocks, one block per wave;
-// orders 7-9 use one wave per SIMD for the larger accumulator set)
+// orders 7-9 use one wave per SIMD for the larger accumulator set; at
+// p = 5, 6 and 7, T1 is the largest with one stored level-2 window per
+// thread, T1 ((p-1)(2p-1) + p) <= NT: two per thread cost registers, and
+// spills at p = 6 in FP64; p = 8 takes 2 rows when level 2 runs on the vector
+// ALU and 4 on the matrix cores, see A12Shape)
 template <> struct A12Cfg<2> { static constexpr int NT = 512, T1 = 42; };
 template <> struct A12Cfg<3> { static constexpr int NT = 512, T1 = 25; };
 template <> struct A12Cfg<4> { static constexpr int NT = 512, T1 = 18; };
-template <> struct A12Cfg<5> { static constexpr int NT = 512, T1 = 14; };
-template <> struct A12Cfg<6> { static constexpr int NT = 512, T1 = 11; };
-template <> struct A12Cfg<7> { static constexpr int NT = 256, T1 = 4; };
+template <> struct A12Cfg<5> { static constexpr int NT = 512, T1 = 12; };
+template <> struct A12Cfg<6> { static constexpr int NT = 512, T1 = 8; };
+template <> struct A12Cfg<7> { static constexpr int NT = 256, T1 = 3; };
 template <> struct A12Cfg<8> { static constexpr int NT = 256, T1 = 4; };
 template <> struct A12Cfg<9> { static constexpr int NT = 256, T1 = 3; };
 
@@ -133,7 +137,8 @@ __device__ __forceinline__ void half_window(int kh, int &c1, int &c2)
     }
 }
 
-template <int P, bool STIFF>
+// L2M: where level 2 runs (0 vector ALU, 1 FP64 matrix cores, 2 bf16 split)
+template <int P, bool STIFF, int L2M>
 struct A12Shape {
     static constexpr int W = 2 * P - 1;          // band width per direction
     static constexpr int NH = half_windows(P);    // stored level-2 windows (c1, c2) per row
@@ -141,7 +146,7 @@ struct A12Shape {
     static constexpr int NG = STIFF ? 4 : 1;     // groups sharing the direction-3 tables
     static constexpr int NCOMP = STIFF ? 6 : 1;  // symmetric coefficient components
     static constexpr int NT = A12Cfg<P>::NT;
-    static constexpr int T1 = A12Cfg<P>::T1;     // rows m1 per tile (max)
+    static constexpr int T1 = (P == 8 && L2M == 0) ? 2 : A12Cfg<P>::T1;   // rows m1 per tile (max)
     // waves per SIMD the register allocation must allow: two workgroups per CU
     // for p <= 4 (their LDS holds two), one above
     static constexpr int WPE = P <= 4 ? 2 * NT / 256 : NT / 256;
@@ -161,10 +166,10 @@ struct A12Shape {
     static constexpr int NBW = (NCB + NW - 1) / NW;              // column blocks per wave
 };
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 constexpr size_t a12_lds_bytes()
 {
-    using S = A12Shape<P, STIFF>;
+    using S = A12Shape<P, STIFF, L2M>;
     size_t a = sizeof(CT) * (size_t)(S::NSLICE + S::L1SZ);
     a = (a + 15) / 16 * 16;
     return a + sizeof(double) * (size_t)(2 * P * P * S::XE + 2 * 2 * P * P) +
@@ -188,7 +193,7 @@ template <int P, bool STIFF, typename CT, int L2M>
 __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__restrict__ C, CT *__restrict__ A2,
                                             int q3base, int T1r, int bx, int by)
 {
-    using S = A12Shape<P, STIFF>;
+    using S = A12Shape<P, STIFF, L2M>;
     constexpr int W = S::W, NP = S::NP, NG = S::NG, NCOMP = S::NCOMP, NT = S::NT, T1 = S::T1, XE = S::XE;
     constexpr int NH = S::NH;
     constexpr int NP1 = STIFF ? 8 : 1;                  // pairs formed at level 1
@@ -575,7 +580,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
 }
 
 template <int P, bool STIFF, typename CT, int L2M>
-__global__ __launch_bounds__((A12Shape<P, STIFF>::NT), (A12Shape<P, STIFF>::WPE)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
+__global__ __launch_bounds__((A12Shape<P, STIFF, L2M>::NT), (A12Shape<P, STIFF, L2M>::WPE)) void asm12_kernel(PatchView pv, const CT *__restrict__ C,
                                                                         CT *__restrict__ A2, int q3base, int T1r)
 {
     asm12_block<P, STIFF, CT, L2M>(pv, C, A2, q3base, T1r, blockIdx.x, blockIdx.y);
@@ -953,25 +958,33 @@ bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_byt
     return pv.d == 3 && a2_chunk(pv, op, prec, ws_bytes) == pv.dir[2].K;
 }
 
-template <int P> static int a12_rows() { return A12Cfg<P>::T1; }
+// level 2 in FP64 mode: matrix cores at p = 4 and 8, vector ALU otherwise
+template <int P> constexpr int f64_level2() { return (P == 4 || P == 8) ? 1 : 0; }
 
-int asm12_max_rows(int P)
+template <int P> static int a12_rows(Prec prec)
+{
+    if (prec == Prec::F64) return A12Shape<P, true, f64_level2<P>()>::T1;
+    if (prec == Prec::BF16X3) return A12Shape<P, true, 2>::T1;
+    return A12Shape<P, true, 0>::T1;
+}
+
+int asm12_max_rows(int P, Prec prec)
 {
     switch (P) {
-    case 2: return a12_rows<2>();
-    case 3: return a12_rows<3>();
-    case 4: return a12_rows<4>();
-    case 5: return a12_rows<5>();
-    case 6: return a12_rows<6>();
-    case 7: return a12_rows<7>();
-    case 8: return a12_rows<8>();
-    default: return a12_rows<9>();
+    case 2: return a12_rows<2>(prec);
+    case 3: return a12_rows<3>(prec);
+    case 4: return a12_rows<4>(prec);
+    case 5: return a12_rows<5>(prec);
+    case 6: return a12_rows<6>(prec);
+    case 7: return a12_rows<7>(prec);
+    case 8: return a12_rows<8>(prec);
+    default: return a12_rows<9>(prec);
     }
 }
 
-void asm12_blocks(const PatchView &pv, int t1, int &gx, int &gy, int &T1r)
+void asm12_blocks(const PatchView &pv, Prec prec, int t1, int &gx, int &gy, int &T1r)
 {
-    const int tmax = asm12_max_rows(pv.P);
+    const int tmax = asm12_max_rows(pv.P, prec);
     if (t1 <= 0 || t1 > tmax) t1 = tmax;
     const int N1 = pv.dir[0].N;
     const int ntile = (N1 + t1 - 1) / t1;
@@ -990,10 +1003,10 @@ void asm3_blocks(const PatchView &pv, int seg, int &gx, int &gy, int &gz, int &L
     gz = nseg;
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t set_asm12_lds(const void *fn)
 {
-    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
+    const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -1001,11 +1014,11 @@ template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, void *ws, size_t ws_bytes,
                                hipStream_t s, int t1, int seg)
 {
-    using S = A12Shape<P, STIFF>;
-    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
+    using S = A12Shape<P, STIFF, L2M>;
+    const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();
     static bool lds_set = false;     // per instantiation: raise the dynamic LDS limit once
     if (!lds_set) {
-        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_kernel<P, STIFF, CT, L2M>);
+        hipError_t e = set_asm12_lds<P, STIFF, CT, L2M>((const void *)asm12_kernel<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
         lds_set = true;
     }
@@ -1015,7 +1028,7 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
     if (chunk == 0 || !ws) return hipErrorInvalidValue;
     const int N3 = pv.dir[2].N, K3 = pv.dir[2].K;
     int ntile, nplane, T1r, gx3, gy3, nseg, L;
-    asm12_blocks(pv, t1, ntile, nplane, T1r);
+    asm12_blocks(pv, L2M == 2 ? Prec::BF16X3 : prec, t1, ntile, nplane, T1r);
     asm3_blocks(pv, seg, gx3, gy3, nseg, L);
     CT *A2 = static_cast<CT *>(ws);
     for (int s0 = 0; s0 < K3; s0 += chunk) {
@@ -1035,7 +1048,7 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
 // Persistent forms: each workgroup takes blocks it = blockIdx.x, + gridDim.x,
 // ... of the concatenated per-patch grids (every patch in one chunk).
 template <int P, bool STIFF, typename CT, int L2M>
-__global__ __launch_bounds__((A12Shape<P, STIFF>::NT), (A12Shape<P, STIFF>::WPE)) void asm12_persistent(TaskList tl)
+__global__ __launch_bounds__((A12Shape<P, STIFF, L2M>::NT), (A12Shape<P, STIFF, L2M>::WPE)) void asm12_persistent(TaskList tl)
 {
     for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
         const int t = task_of(tl.off, tl.ntask, it);
@@ -1066,12 +1079,12 @@ static hipError_t launch_asm12_batch_t(const TaskList &tl, int nblocks, hipStrea
 {
     static bool lds_set = false;
     if (!lds_set) {
-        hipError_t e = set_asm12_lds<P, STIFF, CT>((const void *)asm12_persistent<P, STIFF, CT, L2M>);
+        hipError_t e = set_asm12_lds<P, STIFF, CT, L2M>((const void *)asm12_persistent<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
         lds_set = true;
     }
-    constexpr int NT = A12Shape<P, STIFF>::NT;
-    const size_t lds = a12_lds_bytes<P, STIFF, CT>();
+    constexpr int NT = A12Shape<P, STIFF, L2M>::NT;
+    const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();
     hipLaunchKernelGGL((asm12_persistent<P, STIFF, CT, L2M>), dim3(nblocks), dim3(NT), lds, s, tl);
     return hipGetLastError();
 }
@@ -1086,7 +1099,6 @@ static hipError_t launch_asm3_batch_t(const TaskList &tl, int nblocks, hipStream
 // Level 2 in FP64: on the matrix cores where the full slot tiles win (p = 4,
 // 8), on the vector ALU over the stored windows only for the other orders
 // (FP64 matrix cores and vector FMA have the same peak on this chip).
-template <int P> constexpr int f64_level2() { return (P == 4 || P == 8) ? 1 : 0; }
 
 template <int P>
 static hipError_t launch_batch_p(int which, const TaskList &tl, int op, Prec prec, int nblocks, hipStream_t s)

@@ -110,10 +110,10 @@ bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_byt
 // Batched (persistent) kernels of one order P; nblocks = workgroups of the
 // persistent grid.  Block shapes of one task for the tunable parameter
 // (0 = the single-patch default):
-void asm12_blocks(const PatchView &pv, int t1, int &gx, int &gy, int &T1r);   // t1: rows m1 per tile
+void asm12_blocks(const PatchView &pv, Prec prec, int t1, int &gx, int &gy, int &T1r);   // t1: rows m1 per tile
 void asm3_blocks(const PatchView &pv, int seg, int &gx, int &gy, int &gz, int &L);  // seg: rows m3 per segment
 void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &LZ);  // lz: layers per workgroup
-int asm12_max_rows(int P);
+int asm12_max_rows(int P, Prec prec);
 hipError_t launch_asm12_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);
 hipError_t launch_asm3_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);
 hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s);

@@ -448,7 +448,7 @@ static sf_status tune_assembly(sf_patch *p, int oi, int pi, double *dst)
     }
     hipStream_t s = p->ctx->stream;
     const Prec prec = asm_prec(pi);
-    const int tmax = asm12_max_rows(p->P);
+    const int tmax = asm12_max_rows(p->P, prec);
     std::vector<int> t1s;
     for (int t : {tmax, (3 * tmax + 3) / 4, (tmax + 1) / 2, (tmax + 2) / 3})
         if (t >= 1 && std::find(t1s.begin(), t1s.end(), t) == t1s.end()) t1s.push_back(t);
@@ -655,7 +655,7 @@ static HostTasks build_tasks(const sf_batch *b, int kernel, int P, int oi, int p
         const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
         T.gy = T.gz = 1;
         switch (kernel) {
-        case KASM12: asm12_blocks(p->view, param, T.gx, T.gy, T.arg); break;
+        case KASM12: asm12_blocks(p->view, asm_prec(pi), param, T.gx, T.gy, T.arg); break;
         case KASM3:
             asm3_blocks(p->view, param, T.gx, T.gy, T.gz, T.arg);
             T.out = io.vals[oi] + z0;
@@ -728,7 +728,7 @@ static sf_status tune(sf_batch *b, int kernel, int P, int oi, int pi, const Batc
         }
     std::vector<int> params, mults = {1, 2};
     if (kernel == KASM12) {
-        const int tmax = asm12_max_rows(P);
+        const int tmax = asm12_max_rows(P, asm_prec(pi));
         for (int t : {tmax, (3 * tmax + 3) / 4, (tmax + 1) / 2, (tmax + 2) / 3})
             if (t >= 1 && std::find(params.begin(), params.end(), t) == params.end()) params.push_back(t);
     } else if (kernel == KASM3) {
