@@ -105,7 +105,7 @@ def test_3d_fp32_mode(K, p):
 
 
 @pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((13, 4, 6), 3), ((21, 3, 5), 4), ((3, 4, 3), 5), ((2, 3, 2), 6),
-                                 ((2, 2, 2), 8)])
+                                 ((2, 3, 2), 7), ((2, 2, 2), 8)])
 def test_3d_bf16_split_mode(K, p):
     """Level 2 of the assembly on bf16 matrix cores with hi/lo split operands
     and FP32 accumulation (FP32 coefficients and level 1, FP64 level 3 and
@@ -115,6 +115,14 @@ def test_3d_bf16_split_mode(K, p):
     res = _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_BF16_SPLIT, tol=TOLBF)
     # the split keeps far more than bf16 alone (2^-9 ~ 2e-3) would
     assert max(eA for eA, _ in res.values()) < 1e-4
+
+
+@pytest.mark.parametrize("K,p", [((2, 3, 2), 7), ((2, 2, 2), 8), ((1, 1, 2), 9)])
+def test_3d_fp32_high_order(K, p):
+    """FP32 contractions at orders 7-9, where the level-1/2 tiles are 3, 2
+    and 3 rows m1 high: several tiles per plane and a ragged last one."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=5)
+    _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP32, tol=TOL32)
 
 
 @pytest.mark.parametrize("K,p", [((17,), 2), ((5,), 5), ((30,), 9)])
