@@ -105,7 +105,7 @@ def test_3d_fp32_mode(K, p):
 
 
 @pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((13, 4, 6), 3), ((21, 3, 5), 4), ((3, 4, 3), 5), ((2, 3, 2), 6),
-                                 ((2, 3, 2), 7), ((2, 2, 2), 8)])
+                                 ((2, 3, 2), 7), ((2, 2, 2), 8), ((1, 1, 2), 9)])
 def test_3d_bf16_split_mode(K, p):
     """Level 2 of the assembly on bf16 matrix cores with hi/lo split operands
     and FP32 accumulation (FP32 coefficients and level 1, FP64 level 3 and
