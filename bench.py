@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the sum-factorized IGA hot path on one MI355X.
 
-Default workload: d = 3, 48^3 elements, order p = 4, perturbed-Greville
-geometry, a(x) = 1 + 0.5 sin(2 pi x1) sin(2 pi x2) sin(2 pi x3), stiffness,
-FP64.  One step = the whole hot path on inputs resident in HBM:
-  geometry step (Jacobian, inverse, determinant folded into the coefficient
-  tensor) -> CSR pattern -> global sum-factorized assembly -> one
-  matrix-free apply y = K x.
-The 1D tables are built once at patch creation (host, cost sum p^2 #X) and
-reported separately.
+Default workload (``--workload large``): d = 3, 128^3 elements, order p = 6
+(N = 2,352,637 functions, 2,942,649,737 nonzeros, 452,984,832 quadrature
+points), perturbed-Greville geometry, a(x) = 1 + 0.5 sin(2 pi x1) sin(2 pi x2)
+sin(2 pi x3), stiffness, FP64.  One step = the whole hot path on inputs
+resident in HBM:
+  geometry step (Jacobian, inverse and determinant folded into the
+  coefficient tensor, FP64) -> CSR pattern -> global sum-factorized assembly
+  -> 100 matrix-free applies y = K x.
+The same step then runs in the reduced-precision modes (FP32 contractions,
+BF16 split) for a few steps each, with their errors against the oracle on the
+same sampled rows ("mixed vs FP64 at stated error").  ``--workload single``
+is the 48^3 order-4 patch with one apply per step.
 
-Prints one JSON line.  ``value`` is the assembly throughput of the whole
-step: nnz / step time, in Gnnz/s.
+Prints one JSON line.  ``value`` is the throughput of the whole step in
+nonzeros per second: nnz / step time, in Gnnz/s.
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,23 +32,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "matrix-free apply GDoF/s + assembly Gnnz/s, mixed vs FP64 at stated rel. error"
 PEAK_FP64_TFLOPS = 78.6          # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 COPY_BYTES = 1 << 30
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_assembly_d3_48_p4_fp64.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1809_05471_amd", "csrc")
 
 
-def measured_traffic(source):
-    """HBM bytes of one assembly call from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE of its kernels, each scaled by the same counter
-    on a plain copy of known size); None if the kernels changed since."""
-    import hashlib
+def measured_traffic(name, sources):
+    """HBM bytes per dispatch of the kernels listed in a committed counter
+    summary ``profiles/<name>`` (FETCH_SIZE and WRITE_SIZE, each scaled by
+    the same counter on a plain device copy of known size); None if the file
+    is missing or the kernel sources changed since the counters were taken."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(os.path.join(PROFILES, name)):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        h = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        h = hashlib.sha256(b"".join(open(os.path.join(CSRC, s), "rb").read() for s in sources)).hexdigest()
         if kv.get("source_sha256") != h:
             return None
         cb = float(kv["copy_bytes"])
@@ -85,21 +93,37 @@ def apply_flops(K, p, op):
     return 2 * fwd + 2 * Q[0] * Q[1] * Q[2]
 
 
+def coef_bytes_per_point(prec_name, op="stiff"):
+    """Stored bytes of the folded coefficient tensor per quadrature point."""
+    nc = 6 if op == "stiff" else 1
+    return nc * {"fp64": 8, "fp32": 4, "bf16": 4}[prec_name]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["single", "large", "sweep", "batched"], default="single",
-                    help="single: d=3 48^3 order 4 (the headline line); large: 128^3 order 6 with 100 applies per "
-                         "step; sweep: matrix-free apply at N = 126^3 for orders 2..9; batched: 512 patches")
-    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default=None)
-    ap.add_argument("--elements", type=int, default=48)
-    ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--applies", type=int, default=1, help="matrix-free applies per step")
-    ap.add_argument("--cpu-sample-elements", type=int, default=48,
-                    help="elements per direction of the patch the oracle assembles for the CPU baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched"], default="large",
+                    help="large: d=3 128^3 order 6, geometry + pattern + assembly + 100 applies per step (the "
+                         "headline line); single: 48^3 order 4 with one apply; sweep: matrix-free apply at "
+                         "N = 126^3 for orders 2..9; batched: 512 patches")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default=None,
+                    help="precision of the timed step (default fp64; sweep and batched: see their help)")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="steps timed per reduced-precision mode after the headline (0: skip)")
+    ap.add_argument("--applies", type=int, default=None, help="matrix-free applies per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (errors and CPU timing)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of %d bytes first (scale factor for HBM counters)" % COPY_BYTES)
     return ap.parse_args()
@@ -113,23 +137,58 @@ def main():
         sys.exit(2)
     import torch
 
-    import paper_1809_05471_amd as sf
-    from paper_1809_05471_amd import inputs
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # plain device copy of known size, for scaling the HBM counters of a profiled run
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "sweep":
         return run_sweep(args)
     if args.workload == "batched":
         return run_batched(args)
-    if args.workload == "large":
-        args.elements, args.order = 128, 6
-        args.applies = max(args.applies, 100)
-        args.prec = args.prec or "fp32"
-        args.no_cpu_baseline = True
-    prec = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "bf16": sf.SF_BF16_SPLIT}[args.prec or "fp64"]
-    K = (args.elements,) * 3
-    p = args.order
+    return run_patch(args)
+
+
+def _sample_rows(P, p, precs_bytes):
+    """Rows for the error check: first / middle / last index per direction,
+    the clipped-band indices 1, p-2, N-p+1, N-2 one direction at a time, and
+    rows just after every level-3 chunk boundary of the assembly (entries
+    summed over two chunks)."""
+    n = P.nfun
+    base = [[0, v // 2, v - 1] for v in n]
+    clip = [[1, p - 2, v - p + 1, v - 2] for v in n]
+    idx = set()
+    for j in range(4):
+        axes = [clip[k] if k == j - 1 else base[k] for k in range(3)]
+        for a in axes[0]:
+            for b in axes[1]:
+                for c in axes[2]:
+                    idx.add((a, b, c))
+    hw = (p - 1) * (2 * p - 1) + p
+    plane = 4 * n[1] * n[0] * hw
+    layers = min(max((4096 << 20) // (plane * 8 * p), p - 1), P.nel[2])
+    for eb in precs_bytes:
+        chunk = min(layers * 8 // eb, P.nel[2])
+        for s0 in range(chunk, P.nel[2], chunk):
+            for m3 in range(s0, min(s0 + p - 1, n[2])):
+                idx.add((n[0] // 2, n[1] // 2, m3))
+    return np.array(sorted(a + n[0] * (b + n[1] * c) for a, b, c in idx), dtype=np.int64)
+
+
+def run_patch(args):
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    large = args.workload == "large"
+    K, p = ((128, 128, 128), 6) if large else ((48, 48, 48), 4)
+    applies = args.applies if args.applies is not None else (100 if large else 1)
+    head_prec = args.prec or "fp64"
+    precs = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "bf16": sf.SF_BF16_SPLIT}
     w = inputs.workload_3d(K, p)
     stream = torch.cuda.current_stream()
     ctx = sf.sf_ctx_create(0, stream.cuda_stream)
@@ -144,7 +203,7 @@ def main():
     x = torch.as_tensor(w["x"]).cuda()
     y = torch.empty(N, dtype=torch.float64, device="cuda")
 
-    def step(ev):
+    def step(prec, ev):
         if ev:
             ev[0].record(stream)
         # geometry step queued without a host round trip; its det J test is
@@ -158,81 +217,186 @@ def main():
         sf.sf_assemble(ctx, h, sf.SF_STIFF, prec, val_stiff=vals)
         if ev:
             ev[3].record(stream)
-        for _ in range(args.applies):
+        for _ in range(applies):
             sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
         if ev:
             ev[4].record(stream)
 
-    if args.calibrate_copy:
-        # plain device copy of known size, for scaling the HBM counters of a profiled run
-        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec, None)
+        # HIP events on the library's stream (torch's current stream, handed to the context)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
         torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
-        step(None)
-    # HIP events on the library's stream (torch's current stream, handed to the context)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sf.sf_patch_geometry_check(ctx, h)             # raises SfError(SF_EGEOM) on det J <= 0
-    ms_per_step = (t1 - t0) / args.steps * 1e3
-    stage_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(axis=0)
-    geom_ms, pat_ms, asm_ms, app_ms = stage_ms.tolist()
-    app_ms /= args.applies
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(prec, evs[k])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sf.sf_patch_geometry_check(ctx, h)             # raises SfError(SF_EGEOM) on det J <= 0
+        st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(axis=0)
+        return (t1 - t0) / steps * 1e3, st.tolist()
+
+    def device_rows(rows):
+        rpn = rp.cpu().numpy()
+        segs = [np.arange(rpn[r], rpn[r + 1]) for r in rows]
+        gidx = torch.as_tensor(np.concatenate(segs)).cuda()
+        vg, cg = vals[gidx].cpu().numpy(), ci[gidx].cpu().numpy()
+        out, o = [], 0
+        for sg in segs:
+            out.append((cg[o:o + len(sg)].astype(np.int64), vg[o:o + len(sg)]))
+            o += len(sg)
+        return out, y.cpu().numpy()[rows]
+
+    ms_step, (geom_ms, pat_ms, asm_ms, app_ms) = timed(precs[head_prec], args.steps, args.warmup)
+    app_ms /= applies
+    # sampled rows of every mode's results, for the error check against the oracle
+    got = {}
+    oracle_rows = None
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Problem(w["knots"], p, w["ctrl"], w["coef"])
+        oracle_rows = _sample_rows(P, p, (8, 4))
+        got[head_prec] = device_rows(oracle_rows)
+
+    # reduced-precision modes of the same step ("mixed vs FP64")
+    modes = {}
+    if args.mixed_steps > 0:
+        for name in ("fp64", "fp32", "bf16"):
+            if name == head_prec:
+                continue
+            try:
+                ms, (g_ms, p_ms, a_ms, y_ms) = timed(precs[name], args.mixed_steps, 1)
+            except sf.SfError as e:          # a mode the library does not build
+                modes[name] = {"status": str(e)}
+                continue
+            modes[name] = {"ms_per_step": ms, "value_gnnz_s": nnz / (ms * 1e-3) / 1e9,
+                           "stages_ms": {"geometry": g_ms, "pattern": p_ms, "assembly": a_ms,
+                                         "apply": y_ms / applies},
+                           "assembly_gnnz_s": nnz / (a_ms * 1e-3) / 1e9,
+                           "apply_gdof_s": N / (y_ms / applies * 1e-3) / 1e9,
+                           "apply_hbm_frac": (Q * coef_bytes_per_point(name) + 16 * N)
+                           / (y_ms / applies * 1e-3) / 1e9 / PEAK_HBM_GBS}
+            if oracle_rows is not None:
+                got[name] = device_rows(oracle_rows)
 
     fl_asm = assembly_flops(K, p, "stiff")
     fl_app = apply_flops(K, p, "stiff")
-    esz = 8 if prec == sf.SF_FP64 else 4
-    c_bytes = 6 * Q * esz
+    c_bytes = Q * coef_bytes_per_point(head_prec)
     asm_bytes = c_bytes + nnz * 8
     app_bytes = c_bytes + 2 * N * 8
     asm_tflops = fl_asm / (asm_ms * 1e-3) / 1e12
-    traffic = measured_traffic(os.path.join(ROOT, "paper_1809_05471_amd", "csrc", "assemble.hip")) \
-        if (K, p, prec) == ((48, 48, 48), 4, sf.SF_FP64) else None
-    roofline = {"kernel": "assembly (asm12_kernel levels 1-2 + asm3_kernel level 3, one sf_assemble call)",
-                "bound": "alu", "achieved": asm_tflops,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": asm_tflops / PEAK_FP64_TFLOPS,
-                "traffic": traffic,
-                "algorithmic_flops": fl_asm, "algorithmic_bytes": asm_bytes,
-                "achieved_GBs": asm_bytes / (asm_ms * 1e-3) / 1e9}
+    asm_peak = PEAK_FP64_TFLOPS if head_prec == "fp64" else PEAK_FP32_TFLOPS
+    tag = "d3_128_p6" if large else "d3_48_p4"
+    asm_traffic = measured_traffic(f"traffic_assembly_{tag}_{head_prec}.txt", ["assemble.hip"])
+    app_traffic = measured_traffic(f"traffic_apply_{tag}_{head_prec}.txt", ["apply.hip"])
+    roof_asm = {"kernel": "assembly (asm12_kernel levels 1-2 + asm3_kernel level 3, one sf_assemble call)",
+                "bound": "alu", "achieved": asm_tflops, "peak": asm_peak, "unit": "TFLOP/s",
+                "frac": asm_tflops / asm_peak, "traffic": asm_traffic, "algorithmic_flops": fl_asm,
+                "algorithmic_bytes": asm_bytes, "achieved_GBs": asm_bytes / (asm_ms * 1e-3) / 1e9}
+    app_gbs = app_bytes / (app_ms * 1e-3) / 1e9
+    roof_app = {"kernel": "apply3d_kernel (one sf_apply: y cleared by a fill kernel, then the apply)",
+                "bound": "hbm", "achieved": app_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": app_gbs / PEAK_HBM_GBS, "traffic": app_traffic, "algorithmic_bytes": app_bytes,
+                "algorithmic_flops": fl_app, "achieved_TFLOPs": fl_app / (app_ms * 1e-3) / 1e12}
+    # the dominant kernel of the step: the applies at 128^3 (100 per step), else the assembly
+    dominant = roof_app if applies * app_ms > asm_ms else roof_asm
     out = {
         "metric": METRIC,
-        "value": nnz / (ms_per_step * 1e-3) / 1e9,
+        "value": nnz / (ms_step * 1e-3) / 1e9,
         "unit": "Gnnz/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {sf.SF_FP64: "f64", sf.SF_FP32: "f32", sf.SF_BF16_SPLIT: "bf16x3+f32"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16x3+f32"}[head_prec],
         "data": "synthetic",
-        "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_assembly_plus_"
-                               f"{args.applies}_apply",
+        "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_geometry_pattern_assembly_"
+                               f"plus_{applies}_applies",
                    "d": 3, "elements": list(K), "order": p, "ndof": N, "nnz": nnz, "nquad": Q,
                    "coefficient": "1+0.5*sin(2pi x1)sin(2pi x2)sin(2pi x3)",
-                   "precision": args.prec or "fp64", "applies_per_step": args.applies},
+                   "precision": head_prec, "applies_per_step": applies},
         "stages_ms": {"geometry": geom_ms, "pattern": pat_ms, "assembly": asm_ms, "apply": app_ms,
-                      "tables_host_once": t_tab * 1e3},
+                      "applies_total": app_ms * applies, "tables_host_once": t_tab * 1e3},
         "assembly_gnnz_s": nnz / (asm_ms * 1e-3) / 1e9,
         "apply_gdof_s": N / (app_ms * 1e-3) / 1e9,
-        "apply_hbm_frac": app_bytes / (app_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-        "apply_tflops": fl_app / (app_ms * 1e-3) / 1e12,
-        "roofline": roofline,
+        "apply_hbm_frac": app_gbs / PEAK_HBM_GBS,
+        "roofline": dominant,
+        "roofline_assembly": roof_asm,
+        "roofline_apply": roof_app,
+        "modes": modes,
     }
-
-    if not args.no_cpu_baseline:
-        out.update(cpu_leg(args, w, h, ctx, rp, ci, vals, y, K, p, prec))
     sf.sf_patch_destroy(h)
     sf.sf_ctx_destroy(ctx)
+    del vals, ci, rp, x, y
+    torch.cuda.empty_cache()
+    if oracle_rows is not None:
+        out.update(cpu_leg(P, w, p, K, N, nnz, applies, oracle_rows, got, head_prec, modes))
     print(json.dumps(out), flush=True)
+
+
+def cpu_leg(P, w, p, K, N, nnz, applies, rows, got, head_prec, modes):
+    """Oracle leg: errors of every mode's GPU results on the sampled rows, and
+    the oracle's own throughput on sub-boxes of the same recipe, scaled to the
+    full patch by element count (its cost is the same per element)."""
+    import oracle
+    from paper_1809_05471_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    x = w["x"]
+    ref = P.rows(oracle.STIFF, rows, threads)
+    vmax = max(np.abs(v).max() for _, v in ref)
+    yref = np.array([v @ x[c] for c, v in ref])
+    scale = max(np.abs(v) @ np.abs(x[c]) for c, v in ref)
+    errs = {}
+    for name, (rws, yg) in got.items():
+        for (c, v), (cg, vg) in zip(ref, rws):
+            assert np.array_equal(c, cg), "pattern differs from the oracle's"
+        eA = max(np.abs(vg - v).max() for (_, v), (_, vg) in zip(ref, rws)) / vmax
+        ey = np.abs(yg - yref).max() / scale
+        errs[name] = (float(eA), float(ey))
+    for name in modes:
+        if name in errs:
+            modes[name]["err_A"], modes[name]["err_y"] = errs[name]
+
+    # oracle timing on sub-boxes: all threads on ks^3 elements, one thread on k1^3
+    ks, k1 = (10, 4) if p >= 6 else (24, 8)
+    ws = inputs.workload_3d((ks,) * 3, p)
+    Ps = oracle.Problem(ws["knots"], p, ws["ctrl"], ws["coef"])
+    pat = Ps.pattern()
+    t0 = time.perf_counter()
+    Ps.assemble(oracle.STIFF, threads, pattern=pat)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ps.apply(oracle.STIFF, ws["x"], threads)
+    t_app = time.perf_counter() - t0
+    w1 = inputs.workload_3d((k1,) * 3, p)
+    P1 = oracle.Problem(w1["knots"], p, w1["ctrl"], w1["coef"])
+    pat1 = P1.pattern()
+    t0 = time.perf_counter()
+    P1.assemble(oracle.STIFF, 1, pattern=pat1)
+    t_asm1 = time.perf_counter() - t0
+    nel_full = K[0] * K[1] * K[2]
+    f, f1 = nel_full / ks ** 3, nel_full / k1 ** 3
+    t_step = t_asm * f + applies * t_app * f
+    return {
+        "err_A": errs[head_prec][0], "err_y": errs[head_prec][1], "err_rows_sampled": int(len(rows)),
+        "cpu_baseline": {
+            "value": nnz / t_step / 1e9, "unit": "Gnnz/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"extrapolated: the oracle's element-by-element stiffness assembly (cost N p^3d) and "
+                      f"matrix-free apply of the {ks}^3-element order-{p} patch of the same recipe on {threads} "
+                      f"threads ({t_asm:.2f} s and {t_app:.2f} s), scaled by element count ({f:.0f}x) to the "
+                      f"{K[0]}^3 step of one assembly and {applies} applies",
+            "assembly_s_extrapolated": t_asm * f, "apply_s_extrapolated": t_app * f,
+            "apply_gdof_s": N / (t_app * f) / 1e9,
+            "one_thread": {"sample": f"assembly of the {k1}^3-element patch on 1 thread: {t_asm1:.2f} s",
+                           "assembly_s_extrapolated": t_asm1 * f1,
+                           "assembly_gnnz_s": nnz / (t_asm1 * f1) / 1e9},
+            "seconds": t_asm + t_app + t_asm1},
+    }
 
 
 def _prec_list(args, sf):
@@ -344,50 +508,6 @@ def run_batched(args):
     for h in hs:
         sf.sf_patch_destroy(h)
     sf.sf_ctx_destroy(ctx)
-
-
-def cpu_leg(args, w, h, ctx, rp, ci, vals, y, K, p, prec):
-    """Oracle leg: error of the GPU results on sampled rows, and the oracle's
-    own throughput on a bounded sample of the same recipe."""
-    import torch
-
-    import oracle
-    from paper_1809_05471_amd import inputs
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    torch.cuda.synchronize()
-    P = oracle.Problem(w["knots"], p, w["ctrl"], w["coef"])
-    rng = np.random.default_rng(7)
-    rows = np.unique(np.concatenate([[0, P.N // 2, P.N - 1], rng.integers(0, P.N, 29)]))
-    rpn = rp.cpu().numpy()
-    vn = vals.cpu().numpy()
-    yn = y.cpu().numpy()
-    ref = P.rows(oracle.STIFF, rows, threads)
-    vmax = max(np.abs(v).max() for _, v in ref)
-    eA = max(np.abs(vn[rpn[r]:rpn[r + 1]] - v).max() for r, (_, v) in zip(rows, ref)) / vmax
-    yo = P.apply_rows(oracle.STIFF, w["x"], rows, threads)
-    scale = max(np.abs(v) @ np.abs(w["x"][c]) for c, v in ref)
-    ey = np.abs(yn[rows] - yo).max() / scale
-
-    ks = args.cpu_sample_elements
-    ws = inputs.workload_3d((ks, ks, ks), p)
-    Ps = oracle.Problem(ws["knots"], p, ws["ctrl"], ws["coef"])
-    pat = Ps.pattern()
-    t0 = time.perf_counter()
-    Ps.assemble(oracle.STIFF, threads, pattern=pat)
-    t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    Ps.apply(oracle.STIFF, ws["x"], threads)
-    t_app = time.perf_counter() - t0
-    nnz_s = len(pat[1])
-    return {
-        "err_A": float(eA), "err_y": float(ey), "err_rows_sampled": int(len(rows)),
-        "cpu_baseline": {"value": nnz_s / t_asm / 1e9, "unit": "Gnnz/s", "cores": threads, "kind": "oracle",
-                         "sample": f"oracle element-by-element stiffness assembly (cost N p^3d) of the "
-                                   f"{ks}^3-element order-{p} patch of the same recipe, nnz={nnz_s}, "
-                                   f"{t_asm:.2f} s; matrix-free apply of it {t_app:.2f} s",
-                         "apply_gdof_s": Ps.N / t_app / 1e9,
-                         "seconds": t_asm + t_app},
-    }
 
 
 if __name__ == "__main__":

@@ -26,7 +26,9 @@
  * explicit zeros included, columns ascending; it is shared by the mass and
  * stiffness matrices (Note after the definition of NZ).
  *
- * Supported: d = 1, 2, 3; one order p in 2..9 for all directions; open knot
+ * Supported: d = 1, 2, 3; one order p in 2..9 for all directions (the
+ * descriptor carries one order per direction; unequal orders are
+ * SF_EUNSUPPORTED); open knot
  * vectors with simple interior knots (maximal smoothness), any spacing.
  * Other inputs return SF_EUNSUPPORTED.
  *
@@ -126,7 +128,11 @@ sf_status sf_host_tables_1d(const double *knots, int64_t n_knots, int order, int
  * is a device or a host pointer.  Both are copied at create time. */
 typedef struct {
     int d;                      /* 1..3 */
-    int order;                  /* p = degree + 1, 2..9 */
+    int order[3];               /* p_k = degree + 1 of direction k+1, 2..9 (Sec. 3.2 lets
+                                   every direction have its own order); the kernels
+                                   take one order for all directions: orders that
+                                   differ among the first d entries return
+                                   SF_EUNSUPPORTED; entries k >= d are ignored */
     int64_t n_knots[3];
     const double *knots[3];
     const double *ctrl;

@@ -72,9 +72,11 @@ def _lib():
     lib.orc_apply_rows.argtypes = prob + [ctypes.c_int, f64p, ctypes.c_int64, i64p, f64p,
                                           ctypes.c_int]
     lib.orc_apply.argtypes = prob + [ctypes.c_int, f64p, f64p, ctypes.c_int]
+    lib.orc_apply_elements.argtypes = prob + [ctypes.c_int, f64p, ctypes.c_int64, i64p, f64p,
+                                              ctypes.c_int]
     lib.orc_measure.argtypes = prob + [f64p]
     for f in (lib.orc_pattern, lib.orc_assemble, lib.orc_rows, lib.orc_apply_rows,
-              lib.orc_apply, lib.orc_measure):
+              lib.orc_apply, lib.orc_apply_elements, lib.orc_measure):
         f.restype = ctypes.c_int
     lib.orc_set_defect.argtypes = [ctypes.c_int]
     lib.orc_set_defect.restype = None
@@ -307,6 +309,47 @@ class Problem:
                                           rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                           y.ctypes.data_as(f64), threads))
         return y
+
+    def support_elements(self, rows):
+        """Flattened indices (direction 1 fastest) of the union of the
+        elements in supp phi_m over the given rows; element e activates
+        functions first[e] .. first[e] + p - 1 (open knots)."""
+        rows = np.asarray(rows, dtype=np.int64)
+        mi = []
+        r = rows.copy()
+        for k in range(self.d):
+            mi.append(r % self.nfun[k])
+            r //= self.nfun[k]
+        sel = []
+        for k in range(self.d):
+            first = self.t1d[k]["first"]
+            # element e supports function i iff first[e] <= i <= first[e] + p - 1
+            sel.append([np.nonzero((first <= i) & (i <= first + self.orders[k] - 1))[0] for i in mi[k]])
+        out = set()
+        for j in range(len(rows)):
+            axes = [sel[k][j] for k in range(self.d)]
+            grid = np.meshgrid(*axes, indexing="ij")
+            lin = np.zeros(grid[0].shape, dtype=np.int64)
+            stride = 1
+            for k in range(self.d):
+                lin += grid[k] * stride
+                stride *= self.nel[k]
+            out.update(lin.ravel().tolist())
+        return np.array(sorted(out), dtype=np.int64)
+
+    def apply_rows_by_elements(self, op, x, rows, threads=0):
+        """Rows of A x from the element-by-element product over the union of
+        the rows' supports (the same sum as ``apply``, restricted to the
+        elements those rows need)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        els = np.ascontiguousarray(self.support_elements(rows))
+        y = np.zeros(self.N)
+        kind, val = self._coef_for(op)
+        f64 = ctypes.POINTER(ctypes.c_double)
+        self._check(_lib().orc_apply_elements(*self._args(kind, val), op, x.ctypes.data_as(f64),
+                                              len(els), els.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              y.ctypes.data_as(f64), threads))
+        return y[np.asarray(rows, dtype=np.int64)]
 
     def measure(self):
         out = ctypes.c_double(0.0)

@@ -600,6 +600,75 @@ int orc_apply(PROB_ARGS, int op, const double *x, double *y, int nthreads)
 }
 
 /* sum_x w |det J|: the measure of the physical domain under the rule. */
+/* The element-by-element product of orc_apply restricted to a list of
+ * elements (flattened, direction 1 fastest): y (length N, overwritten) gets
+ * the contributions of those elements only.  A row m of A x is complete in y
+ * when the list holds every element of supp phi_m; the Python side passes the
+ * union of the supports of the rows it wants, so that rows near each other
+ * share their elements' work. */
+int orc_apply_elements(PROB_ARGS, int op, const double *x, int64_t nlist, const int64_t *elems,
+                       double *y, int nthreads)
+{
+    prob_t P;
+    int st = prob_init(&P, PROB_PASS);
+    if (st) return st;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    memset(y, 0, sizeof(double) * P.nfun_total);
+    int ncol = 1;
+    for (int k = 0; k < P.d; ++k) ncol *= P.p[k];
+    int err = ORC_OK;
+    /* colour classes (e_k mod p_k): elements of one class share no function */
+    for (int c = 0; c < ncol && !err; ++c) {
+        int col[MAXD] = {0, 0, 0};
+        { int r = c; for (int k = 0; k < P.d; ++k) { col[k] = r % P.p[k]; r /= P.p[k]; } }
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < nlist; ++i) {
+            int e[MAXD] = {0, 0, 0};
+            int64_t r = elems[i];
+            int skip = 0;
+            for (int k = 0; k < P.d; ++k) {
+                e[k] = (int)(r % P.nel[k]);
+                r /= P.nel[k];
+                if (e[k] % P.p[k] != col[k]) skip = 1;
+            }
+            if (skip) continue;
+            qp_t *Q = malloc(sizeof(qp_t));
+            int nqp = 1;
+            for (int k = 0; k < P.d; ++k) nqp *= P.p[k];
+            for (int q = 0; q < nqp; ++q) {
+                int g[MAXD] = {0, 0, 0};
+                int rr = q;
+                for (int k = 0; k < P.d; ++k) { g[k] = rr % P.p[k]; rr /= P.p[k]; }
+                if (eval_qp(&P, e, g, Q) != ORC_OK) {
+                    #pragma omp atomic write
+                    err = ORC_EGEOM;
+                    break;
+                }
+                double s = Q->wdet * Q->coef;
+                if (op == 1) {
+                    double u = 0.0;
+                    for (int b = 0; b < Q->nloc; ++b) u += x[Q->gidx[b]] * Q->val[b];
+                    for (int a = 0; a < Q->nloc; ++a) y[Q->gidx[a]] += s * u * Q->val[a];
+                } else {
+                    double gu[MAXD] = {0, 0, 0};
+                    for (int b = 0; b < Q->nloc; ++b)
+                        for (int k = 0; k < P.d; ++k) gu[k] += x[Q->gidx[b]] * Q->grad[b][k];
+                    for (int a = 0; a < Q->nloc; ++a) {
+                        double t = 0.0;
+                        for (int k = 0; k < P.d; ++k) t += gu[k] * Q->grad[a][k];
+                        y[Q->gidx[a]] += s * t;
+                    }
+                }
+            }
+            free(Q);
+        }
+    }
+    prob_free(&P);
+    return err;
+}
+
 int orc_measure(PROB_ARGS, double *out)
 {
     prob_t P;

@@ -39,7 +39,7 @@ class SfError(RuntimeError):
 
 
 class PatchDesc(ctypes.Structure):
-    _fields_ = [("d", ctypes.c_int), ("order", ctypes.c_int), ("n_knots", ctypes.c_int64 * 3),
+    _fields_ = [("d", ctypes.c_int), ("order", ctypes.c_int * 3), ("n_knots", ctypes.c_int64 * 3),
                 ("knots", ctypes.POINTER(ctypes.c_double) * 3), ("ctrl", ctypes.c_void_p),
                 ("ctrl_on_device", ctypes.c_int)]
 
@@ -136,10 +136,13 @@ def sf_last_error(ctx):
 
 
 def sf_patch_create(ctx, d, order, knots, ctrl, ctrl_on_device=False):
-    """knots: list of d 1D float64 arrays; ctrl: host numpy [N, d] or a device tensor."""
+    """knots: list of d 1D float64 arrays; order: one int for every direction
+    or a sequence of d ints; ctrl: host numpy [N, d] or a device tensor."""
     desc = PatchDesc()
     desc.d = d
-    desc.order = order
+    orders = [int(order)] * 3 if np.ndim(order) == 0 else [int(o) for o in order] + [0] * (3 - len(order))
+    for k in range(3):
+        desc.order[k] = orders[k]
     keep = []
     for k in range(3):
         if k < d:

@@ -520,13 +520,8 @@ static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double 
 {
     if (pv.d == 3) {
         const size_t lds = apply3d_lds<P, STIFF, CT>();
-        static bool lds_set = false;
-        if (!lds_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)apply3d_kernel<P, STIFF, CT>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            lds_set = true;
-        }
+        hipError_t e = allow_dynamic_lds((const void *)apply3d_kernel<P, STIFF, CT>, lds);
+        if (e != hipSuccess) return e;
         int gx, gy, gz, LZ;
         apply_blocks(pv, lz, gx, gy, gz, LZ);
         hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, x, y,
@@ -546,13 +541,8 @@ template <int P, bool STIFF, typename CT>
 static hipError_t launch_apply_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
 {
     const size_t lds = apply3d_lds<P, STIFF, CT>();
-    static bool lds_set = false;
-    if (!lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)apply3d_persistent<P, STIFF, CT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_set = true;
-    }
+    hipError_t e = allow_dynamic_lds((const void *)apply3d_persistent<P, STIFF, CT>, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((apply3d_persistent<P, STIFF, CT>), dim3(nblocks), dim3(STile<P>::NT), lds, s, tl);
     return hipGetLastError();
 }

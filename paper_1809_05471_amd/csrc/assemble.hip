@@ -1007,7 +1007,7 @@ template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t set_asm12_lds(const void *fn)
 {
     const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return allow_dynamic_lds(fn, lds);
 }
 
 template <int P, bool STIFF, typename CT, int L2M>
@@ -1016,11 +1016,9 @@ static hipError_t launch_asm3d(const PatchView &pv, const CT *C, double *vals, v
 {
     using S = A12Shape<P, STIFF, L2M>;
     const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();
-    static bool lds_set = false;     // per instantiation: raise the dynamic LDS limit once
-    if (!lds_set) {
+    {
         hipError_t e = set_asm12_lds<P, STIFF, CT, L2M>((const void *)asm12_kernel<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
-        lds_set = true;
     }
     const int op = STIFF ? 2 : 1;
     const Prec prec = sizeof(CT) == sizeof(double) ? Prec::F64 : Prec::F32;   // workspace element size
@@ -1077,11 +1075,9 @@ __global__ __launch_bounds__(256) void asm3_persistent(TaskList tl)
 template <int P, bool STIFF, typename CT, int L2M>
 static hipError_t launch_asm12_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
 {
-    static bool lds_set = false;
-    if (!lds_set) {
+    {
         hipError_t e = set_asm12_lds<P, STIFF, CT, L2M>((const void *)asm12_persistent<P, STIFF, CT, L2M>);
         if (e != hipSuccess) return e;
-        lds_set = true;
     }
     constexpr int NT = A12Shape<P, STIFF, L2M>::NT;
     const size_t lds = a12_lds_bytes<P, STIFF, CT, L2M>();

@@ -23,7 +23,7 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
     const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    if (!(det > 0.0)) *o.bad_det = 1;
+    if (!(det > 0.0) && o.bad_det) *o.bad_det = 1;
     const double id = 1.0 / det;
     double inv[3][3];
     inv[0][0] = c00 * id;
@@ -253,7 +253,7 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
         inv[1][0] = -J[1][0] / det;
         inv[1][1] = J[0][0] / det;
     }
-    if (!(det > 0.0)) *o.bad_det = 1;
+    if (!(det > 0.0) && o.bad_det) *o.bad_det = 1;
     double w = d0.W[q0] * (DIM == 2 ? d1.W[q1] : 1.0);
     double wd = w * fabs(det);
     const bool f32 = o.prec == Prec::F32;
@@ -284,13 +284,8 @@ static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream
         using TL = Tile<P>;
         dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
         constexpr size_t lds = geom3d_lds<P>();
-        static bool lds_set = false;
-        if (!lds_set && lds > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute((const void *)geom3d_kernel<P>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            lds_set = true;
-        }
+        hipError_t e = allow_dynamic_lds((const void *)geom3d_kernel<P>, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(geom3d_kernel<P>, grid, dim3(TL::NT), lds, s, pv, o);
     } else {
         int64_t nb = (pv.Q + 255) / 256;

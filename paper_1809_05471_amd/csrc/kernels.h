@@ -87,6 +87,10 @@ __device__ __forceinline__ int task_of(const int64_t *off, int ntask, int64_t it
     return lo;
 }
 
+// Raise the dynamic LDS limit of kernel `fn` to `bytes` on the current
+// device, once per (device, kernel); thread safe.  Needed above 64 KiB.
+hipError_t allow_dynamic_lds(const void *fn, size_t bytes);
+
 hipError_t launch_geometry(const PatchView &pv, const GeomOut &out, hipStream_t s);
 hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
                           int64_t col_base, int64_t nnz_base, hipStream_t s);

@@ -8,7 +8,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -69,6 +71,25 @@ struct sf_batch {
     std::vector<Tuned> tuned;
     std::vector<void *> dev;      // device task lists referenced by the graphs
 };
+
+namespace sfiga {
+
+hipError_t allow_dynamic_lds(const void *fn, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({dev, fn})) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done.insert({dev, fn});
+    return e;
+}
+
+}  // namespace sfiga
 
 namespace {
 
@@ -175,15 +196,20 @@ sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out
     *out = nullptr;
     ctx->err.clear();
     if (desc->d < 1 || desc->d > 3) return fail(ctx, SF_EUNSUPPORTED, "dimension must be 1, 2 or 3");
-    if (desc->order < 1) return fail(ctx, SF_EINVAL, "order must be >= 1");
-    if (desc->order < 2 || desc->order > kMaxOrder)
-        return fail(ctx, SF_EUNSUPPORTED, "order must be in 2..9");
+    for (int k = 0; k < desc->d; ++k) {
+        if (desc->order[k] < 1) return fail(ctx, SF_EINVAL, "order must be >= 1");
+        if (desc->order[k] < 2 || desc->order[k] > kMaxOrder)
+            return fail(ctx, SF_EUNSUPPORTED, "order must be in 2..9");
+        if (desc->order[k] != desc->order[0])
+            return fail(ctx, SF_EUNSUPPORTED, "per-direction orders differ: the kernels take one order for all "
+                                              "directions");
+    }
     if (!desc->ctrl) return fail(ctx, SF_EINVAL, "null control points");
     sf_patch *p = new (std::nothrow) sf_patch;
     if (!p) return fail(ctx, SF_ENOMEM, "host allocation failed");
     p->ctx = ctx;
     p->d = desc->d;
-    p->P = desc->order;
+    p->P = desc->order[0];
     for (int k = 0; k < desc->d; ++k) {
         if (!desc->knots[k]) { delete p; return fail(ctx, SF_EINVAL, "null knot vector"); }
         bool unsup = false;
@@ -301,7 +327,7 @@ sf_status sf_patch_quad_points(sf_patch *p, double *dev_xyz)
     if (!dev_xyz) return fail(p->ctx, SF_EINVAL, "null output");
     GeomOut o{};
     o.xyz = dev_xyz;
-    o.bad_det = p->dflag;
+    o.bad_det = nullptr;          // G only: the det J record belongs to the prepares
     o.prec = Prec::F64;
     o.coef_mass = o.coef_stiff = Coef{0, 1.0, nullptr};
     hipError_t e = launch_geometry(p->view, o, p->ctx->stream);

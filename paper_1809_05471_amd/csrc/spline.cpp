@@ -5,6 +5,11 @@
 
 namespace sfiga {
 
+// Gauss-Legendre rule with p points on [-1, 1]: Newton's method on the
+// Legendre polynomial P_p, evaluated by its three-term (Bonnet) recurrence,
+// started from the classical cosine approximation of the roots; weights
+// 2 / ((1 - z^2) P_p'(z)^2).  A textbook method (e.g. Abramowitz & Stegun,
+// 25.4.29, and the Gauss-Legendre routines of Numerical Recipes), restated.
 void gauss_legendre(int p, std::vector<double> &nodes, std::vector<double> &weights)
 {
     nodes.assign(p, 0.0);
@@ -49,6 +54,9 @@ void gauss_legendre(int p, std::vector<double> &nodes, std::vector<double> &weig
 // Values and first derivatives of the p B-splines of order p that are
 // nonzero on knot span [t[k], t[k+1]) at x, by de Boor's triangular scheme
 // (left/right differences), then the derivative from the order p-1 values.
+// This is the textbook basis-function table (de Boor, "A Practical Guide to
+// Splines"; Piegl & Tiller, "The NURBS Book", algorithms A2.2 and A2.3, whose
+// layout keeps the knot differences in the lower triangle), restated.
 static void basis_funs(const double *t, int k, int p, double x, double *val, double *der)
 {
     const int deg = p - 1;

@@ -92,6 +92,21 @@ class GpuPatch:
         self.close()
 
 
+# measured errors of the session: (test, quantity, precision, value), printed
+# in the terminal summary (tests/conftest.py) so that the bounds can be set
+# from measurements
+MEASURED = []
+
+PREC_NAME = {sf.SF_FP64: "fp64", sf.SF_FP32: "fp32", sf.SF_BF16_SPLIT: "bf16_split",
+             sf.SF_FP16_SPLIT: "fp16_split"}
+
+
+def record(what, prec, value):
+    import os
+    MEASURED.append((os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0], what,
+                     PREC_NAME.get(prec, str(prec)), float(value)))
+
+
 def err_A(v, vref):
     return float(np.abs(v - vref).max() / np.abs(vref).max())
 
@@ -100,19 +115,73 @@ def err_y(y, yref, absAx):
     return float(np.abs(y - yref).max() / np.abs(absAx).max())
 
 
-def sample_rows(nfun, rng, nrandom=64, coarse=False):
+def _lin(idx, nfun):
+    m, stride = 0, 1
+    for k in range(len(nfun)):
+        m += int(idx[k]) * stride
+        stride *= nfun[k]
+    return m
+
+
+def sample_rows(nfun, rng, nrandom=64, coarse=False, p=None, extra=(), band="grid"):
     """Corner, edge, face and interior rows of a tensor grid plus random ones
-    (coarse: only first / middle / last index per direction)."""
+    (coarse: only first / middle / last index per direction).  With the order
+    p, the indices 1, p-2, N-p+1 and N-2 are added in every direction: rows
+    whose 1D band (Corollary on #NZ) is clipped by the boundary; band="grid"
+    takes every combination, band="cross" varies one direction at a time
+    (the others at their first / middle / last index).  `extra` is a list of
+    multi-indices (direction 1 first) added as they are."""
     d = len(nfun)
     picks = set()
-    choices = [[0, n // 2, n - 1] if coarse else [0, 1, n // 2, n - 2, n - 1] for n in nfun]
-    grids = np.meshgrid(*choices, indexing="ij")
-    for idx in zip(*[g.ravel() for g in grids]):
-        m, stride = 0, 1
-        for k in range(d):
-            m += int(idx[k]) * stride
-            stride *= nfun[k]
-        picks.add(m)
+    base, clipped = [], []
+    for n in nfun:
+        c = {0, n // 2, n - 1} if coarse else {0, 1, n // 2, n - 2, n - 1}
+        base.append(sorted(v for v in c if 0 <= v < n))
+        clipped.append(sorted(v for v in {1, p - 2, n - p + 1, n - 2} if 0 <= v < n) if p is not None else [])
+    if band == "grid":
+        sets = [[sorted(set(base[k]) | set(clipped[k])) for k in range(d)]]
+    else:
+        sets = [base] + [[clipped[k] if k == j else base[k] for k in range(d)] for j in range(d)]
+    for choices in sets:
+        grids = np.meshgrid(*choices, indexing="ij")
+        for idx in zip(*[g.ravel() for g in grids]):
+            picks.add(_lin(idx, nfun))
+    for idx in extra:
+        if all(0 <= int(idx[k]) < nfun[k] for k in range(d)):
+            picks.add(_lin(idx, nfun))
     N = int(np.prod(nfun))
     picks.update(int(v) for v in rng.integers(0, N, nrandom))
     return np.array(sorted(picks), dtype=np.int64)
+
+
+def half_windows(p):
+    """Stored level-2 windows per (m1, m2) of the library's assembly: the
+    upper half of the (2p-1)^2 band windows, used to predict its chunks."""
+    return (p - 1) * (2 * p - 1) + p
+
+
+def chunk_boundaries(nfun, nel, p, prec_bytes, ops_groups=4, cap_mb=4096, sized_bytes=8):
+    """Direction-3 element layers where the library's level-1/2 workspace is
+    split into chunks (its rule: the workspace holds as many whole element
+    layers of level-2 partials as fit in the cap, sized for FP64 stiffness;
+    a precision with smaller partials fits proportionally more layers).
+    Returns the first layer s0 > 0 of every chunk."""
+    plane = ops_groups * nfun[1] * nfun[0] * half_windows(p)
+    per_layer_sized = plane * sized_bytes * p
+    K3 = nel[2]
+    layers = min(max((cap_mb << 20) // per_layer_sized, max(p - 1, 1)), K3)
+    ws = layers * per_layer_sized
+    chunk = min(ws // (plane * prec_bytes * p), K3)
+    return list(range(chunk, K3, chunk))
+
+
+def straddle_rows(nfun, nel, p, prec_bytes, picks_12):
+    """Rows m = (m1, m2, m3) with m3 in [s0, s0 + p - 2] for every chunk
+    boundary s0: their entries with n3 in the same range collect level-3
+    sums from both sides of the boundary."""
+    out = []
+    for s0 in chunk_boundaries(nfun, nel, p, prec_bytes):
+        for m3 in range(s0, min(s0 + p - 1, nfun[2])):
+            for m1, m2 in picks_12:
+                out.append((m1, m2, m3))
+    return out

@@ -339,6 +339,29 @@ def test_rows_and_apply_agree_with_full_assembly():
         assert np.abs(y - yref).max() < 1e-14 * scale
         yr = P.apply_rows(op, x, rows)
         assert np.abs(yr - yref[rows]).max() < 1e-14 * scale
+        # the product restricted to the rows' supports gives the same rows
+        ye = P.apply_rows_by_elements(op, x, rows)
+        assert np.abs(ye - yref[rows]).max() < 1e-14 * scale
+
+
+def test_support_elements_are_exactly_the_supports():
+    """The element set of a row is the box of elements whose span meets
+    supp phi_m (p consecutive elements per direction, clipped at the ends),
+    checked against the tables' active functions."""
+    K, p = (6, 4, 5), 3
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=3)
+    P = oracle.Problem(kn, p, ctrl)
+    for m in (0, 7, P.N // 3, P.N - 1):
+        mi = np.unravel_index(m, P.nfun[::-1])[::-1]
+        els = P.support_elements([m])
+        want = []
+        for e3 in range(K[2]):
+            for e2 in range(K[1]):
+                for e1 in range(K[0]):
+                    e = (e1, e2, e3)
+                    if all(e[k] <= mi[k] <= e[k] + p - 1 for k in range(3)):
+                        want.append(e1 + K[0] * (e2 + K[1] * e3))
+        assert np.array_equal(els, np.array(want))
 
 
 def test_folded_geometry_is_rejected():
