@@ -204,6 +204,26 @@ sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col
 sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
                       double *dev_val_mass, double *dev_val_stiff);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * assembly as sf_assemble, with the same kernels, allocating nothing.  The
+ * d = 3 level-2 workspace is a fixed device array of 256 MiB that the
+ * library holds on every device it runs on until the process ends (its
+ * address is looked up by sf_ctx_create); patches run in chunks of element
+ * layers that fit in it.  A patch whose smallest chunk (p - 1 element
+ * layers of level-2 partials) exceeds 256 MiB returns SF_EUNSUPPORTED
+ * (e.g. 128^3 elements at order 6 needs 1 GiB: use sf_assemble).  No
+ * autotuning: tile shapes tuned by an earlier sf_assemble of the same
+ * (operator, precision) are used, else the defaults; they do not change the
+ * values.  Values equal sf_assemble's up to the summation order of entries
+ * that straddle two chunks.  Every call on a device shares that device's
+ * array, and nothing in it needs to start at zero: calls that overlap on one
+ * device (two streams, two threads) race and must be serialized by the
+ * caller.  Otherwise as sf_assemble: needs a prior sf_patch_prepare of the
+ * operators at `prec`, overwrites the outputs, asynchronous. */
+sf_status sf_assemble_noalloc(sf_patch *patch, unsigned ops, sf_precision prec,
+                              double *dev_val_mass, double *dev_val_stiff);
+
 /* Matrix-free product y = A x (Algorithm 3 forward, pointwise coefficient,
  * Algorithm 2 backward) for one operator op; dev_x, dev_y device [N] FP64,
  * y overwritten, x and y must not overlap.  Needs a prior sf_patch_prepare

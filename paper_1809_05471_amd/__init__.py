@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4:
 EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target", "sf_host_tables_1d",
             "sf_patch_create",
             "sf_patch_info", "sf_patch_set_coef", "sf_patch_quad_points", "sf_patch_prepare",
-            "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_apply", "sf_patch_destroy", "sf_batch_create",
+            "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_assemble_noalloc", "sf_apply", "sf_patch_destroy", "sf_batch_create",
             "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_batch_destroy"]
 
 
@@ -67,6 +67,7 @@ def lib():
         "sf_patch_geometry_check": (st, [vp]),
         "sf_csr_pattern": (st, [vp, vp, vp]),
         "sf_assemble": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
+        "sf_assemble_noalloc": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
         "sf_apply": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
         "sf_patch_destroy": (None, [vp]),
         "sf_batch_create": (st, [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
@@ -204,6 +205,10 @@ def sf_csr_pattern(ctx, patch, row_ptr, col_ind):
 
 def sf_assemble(ctx, patch, ops, prec, val_mass=None, val_stiff=None):
     _check(lib().sf_assemble(patch, ops, prec, _ptr(val_mass), _ptr(val_stiff)), ctx)
+
+
+def sf_assemble_noalloc(ctx, patch, ops, prec, val_mass=None, val_stiff=None):
+    _check(lib().sf_assemble_noalloc(patch, ops, prec, _ptr(val_mass), _ptr(val_stiff)), ctx)
 
 
 def sf_apply(ctx, patch, op, prec, x, y):

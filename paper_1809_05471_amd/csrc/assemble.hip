@@ -45,6 +45,9 @@
 // Redundant work: none at levels 1 and 3; level 1 is formed once per
 // (plane, m1 tile, e2); level 3 recomputes the p - 1 element layers before
 // each row segment.
+#include <map>
+#include <mutex>
+
 #include "kernels.h"
 
 #include <cstdlib>
@@ -956,6 +959,40 @@ size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t c
 bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_bytes)
 {
     return pv.d == 3 && a2_chunk(pv, op, prec, ws_bytes) == pv.dir[2].K;
+}
+
+size_t assemble_min_workspace_bytes(const PatchView &pv, int op, Prec prec)
+{
+    if (pv.d != 3) return 0;
+    const int K3 = pv.dir[2].K;
+    const int minl = pv.P - 1 > 1 ? pv.P - 1 : 1;
+    return a2_plane_bytes(pv, op, prec) * pv.P * (size_t)(minl < K3 ? minl : K3);
+}
+
+// Fixed device scratch for the assembly entry point that allocates nothing:
+// the level-2 workspace of one chunk of element layers.  Each device the
+// library runs on holds its own copy until the process ends; in host code the
+// array's name is not a device address, so the address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
 }
 
 // level 2 in FP64 mode: matrix cores at p = 4 and 8, vector ALU otherwise

@@ -110,6 +110,13 @@ hipError_t launch_assemble(const PatchView &pv, int op, Prec prec, const void *c
 size_t assemble_workspace_bytes(const PatchView &pv, int op, Prec prec, size_t cap);
 // true if the workspace holds the whole patch (one chunk)
 bool assemble_single_chunk(const PatchView &pv, int op, Prec prec, size_t ws_bytes);
+// smallest workspace the d = 3 assembly runs with (p - 1 element layers)
+size_t assemble_min_workspace_bytes(const PatchView &pv, int op, Prec prec);
+// Size of the fixed per-device scratch of the assembly entry point that
+// allocates nothing, and its device address on the current device (looked up
+// once per device).
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+hipError_t noalloc_scratch(void **ptr);
 
 // Batched (persistent) kernels of one order P; nblocks = workgroups of the
 // persistent grid.  Block shapes of one task for the tunable parameter

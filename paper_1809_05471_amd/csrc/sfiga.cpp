@@ -23,6 +23,9 @@ struct sf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // device address of the fixed assembly scratch (sf_assemble_noalloc),
+    // looked up at creation with the context's device current
+    void *scratch = nullptr;
 };
 
 struct sf_patch {
@@ -181,6 +184,10 @@ sf_status sf_ctx_create(int device, void *hip_stream, sf_ctx **out)
     if (!c) return SF_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    if (noalloc_scratch(&c->scratch) != hipSuccess) {
+        delete c;
+        return SF_EDEVICE;
+    }
     *out = c;
     return SF_OK;
 }
@@ -540,6 +547,40 @@ sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, 
             if (st != SF_OK) return st;
         }
     return assemble_into(p, ops, pi, vm, vs, p->ctx->stream);
+}
+
+sf_status sf_assemble_noalloc(sf_patch *p, unsigned ops, sf_precision prec, double *vm, double *vs)
+{
+    if (!p) return SF_EINVAL;
+    sf_ctx *ctx = p->ctx;
+    ctx->err.clear();
+    int pi;
+    sf_status st = check_ready(p, ops, prec, pi);
+    if (st != SF_OK) return st;
+    if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(ctx, SF_EINVAL, "null output");
+    if (p->d == 3) {
+        for (int oi = 0; oi < 2; ++oi) {
+            if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
+            const size_t need = assemble_min_workspace_bytes(p->view, oi + 1, asm_prec(pi));
+            if (need > kNoAllocScratchBytes)
+                return fail(ctx, SF_EUNSUPPORTED,
+                            "patch too large for the fixed scratch: " + std::to_string(need >> 20) +
+                                " MiB of level-2 partials for the smallest chunk, scratch " +
+                                std::to_string(kNoAllocScratchBytes >> 20) + " MiB (use sf_assemble)");
+        }
+    }
+    for (int oi = 0; oi < 2; ++oi) {
+        if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
+        double *dst = oi == 0 ? vm : vs;
+        // tile shapes tuned by an earlier sf_assemble if any (they do not
+        // change the values); no tuning here
+        const int t1 = p->tune_t1[oi][pi] > 0 ? p->tune_t1[oi][pi] : 0;
+        const int seg = p->tune_seg[oi][pi] > 0 ? p->tune_seg[oi][pi] : 0;
+        hipError_t e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, ctx->scratch,
+                                       kNoAllocScratchBytes, ctx->stream, t1, seg);
+        if (e != hipSuccess) return hip_fail(ctx, e, "assembly kernel");
+    }
+    return SF_OK;
 }
 
 sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x, double *y)
