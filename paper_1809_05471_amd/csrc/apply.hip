@@ -27,30 +27,99 @@ struct STile {
     static constexpr int NT = (TX * TY + 63) / 64 * 64;
 };
 
+// Per (order, operator, storage type) shape of the d = 3 kernel, chosen by
+// measurement (stiffness, N = 126^3, and 128^3 at order 6):
+//   G      the layer's p quadrature planes go through the plane stages
+//          (forward 2 and 1, pointwise, backward 1 and 2) in G groups of
+//          ceil(p / G) planes: less LDS per workgroup, but more barriers and
+//          less cover for the coefficient loads (it pays only for FP64 at
+//          order 8);
+//   CMODE  how the coefficients reach the pointwise stage: 0 plane by plane
+//          in that stage; 1 the group's planes loaded at the start of the
+//          group (the first group's at the start of the layer, before the
+//          forward direction-3 stage); 2 the next group's planes (the next layer's first group
+//          after the last) loaded right after the pointwise stage, so that
+//          they have the backward stages to arrive;
+//   TWOSTEP backward directions 1 and 2 in two steps (per-element sums in
+//          place, then sums over the elements sharing a function);
+//   UNRJ   the output loop of those per-element sums unrolled: more
+//          independent work per item, but the compiler then holds all p^2
+//          table values of an element in registers (FP64 at order 6: 188
+//          instead of 120 VGPRs, one workgroup per CU instead of two);
+//   XCD    tiles dealt to the XCDs in contiguous ranges (xcd_tile): a tile row
+//          of coefficients is TX values, not a whole number of 128-byte
+//          lines, so neighbouring tiles share the lines at their ends; on one
+//          XCD those are fetched once (128^3 order 6 FP64: 39 -> 27 GB
+//          fetched per apply).  It pays where the kernel waits on HBM (low
+//          orders); from order 5 on the kernel waits on LDS and barriers and
+//          the remap costs 2-6%.
+//   W      minimum resident waves per SIMD asked of the compiler (register cap).
+// Measured at 128^3 order 6 FP64 (ms per apply): 12.43 before the x-row and
+// table prefetch and the parallel backward direction 3, 11.06 after, 7.95
+// with UNRJ = 0; the coefficients of the whole layer in registers (CMODE 1)
+// cost the second workgroup per CU there (16.6).
+struct ApplyShape {
+    int G, CMODE, TWOSTEP, UNRJ, W, XCD;
+};
+
+constexpr ApplyShape apply_shape(int P, bool f64, bool stiff)
+{
+    // BEGIN SHAPES
+    if (!stiff || P == 2) return ApplyShape{1, 2, f64 ? P >= 3 : P >= 5, 1, 1, P == 2 || (!f64 && P <= 4)};
+    if (f64) {
+        if (P <= 4) return ApplyShape{1, P == 4 ? 1 : 0, 1, 1, 1, 0};
+        if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
+        return ApplyShape{1, 0, 1, 0, 1, 0};
+    }
+    if (P == 4) return ApplyShape{1, 0, 0, 1, 1, 1};
+    return ApplyShape{1, 1, P >= 5, 1, 1, P <= 4};
+    // END SHAPES
+}
+
+template <int P, bool STIFF, typename CT>
+struct ApplyCfg {
+    static constexpr ApplyShape S = apply_shape(P, sizeof(CT) == sizeof(double), STIFF);
+    static constexpr int G = S.G;
+    static constexpr int CMODE = S.CMODE;
+    static constexpr bool TWOSTEP = S.TWOSTEP != 0;
+    static constexpr bool UNRJ = S.UNRJ != 0;
+    static constexpr int W = S.W;
+    static constexpr bool XCD = S.XCD != 0;
+};
+
 template <int P, bool STIFF, typename CT>
 __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__restrict__ C,
                                               const double *__restrict__ x, double *__restrict__ y, int LZ, int bx,
                                               int by, int bz)
 {
     using TL = STile<P>;
+    using CF = ApplyCfg<P, STIFF, CT>;
     constexpr int E = TL::E, NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
     constexpr int NF = STIFF ? 3 : 1;      // gradient components or value
     constexpr int NC = STIFF ? 6 : 1;      // coefficient components
     constexpr int PP = P * P, NXY = NX * NY;
-    // stage buffers: sa holds the forward direction-3 results, then the
-    // pointwise results; sb the forward direction-2 results, then the
-    // backward direction-1 results
-    constexpr int SA = (2 * P * NXY > NF * P * TY * TX) ? 2 * P * NXY : NF * P * TY * TX;
+    constexpr int G = CF::G, PG = (P + G - 1) / G;     // plane groups, planes per group
+    constexpr int CMODE = CF::CMODE;
+    constexpr bool TWOSTEP = CF::TWOSTEP;
+    // stage buffers: sa the forward direction-3 results of all planes; sh the
+    // pointwise results and sb the forward direction-2 / backward direction-1
+    // results of one group; sq the backward direction-2 results of all planes.
+    // With one group sa, sh and sq share one buffer (each is dead when the
+    // next one is written).
+    constexpr int SA = 2 * P * NXY, SH = NF * PG * TY * TX, SB = NF * PG * TY * NX;
+    constexpr int SAHQ = G == 1 ? (SA > SH ? SA : SH) : 2 * SA + SH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *xw = reinterpret_cast<CT *>(smem_raw);   // [P slots][NY][NX], slot = n3 mod p
     CT *yw = xw + P * NXY;                       // [P slots][NY][NX]
-    CT *sa = yw + P * NXY;                       // [2][P][NY][NX] forward dir 3
-    CT *sh = sa;                                 // [NF][P][TY][TX] pointwise (sa is dead by then)
-    CT *sb = sa + SA;                            // [NF][P][TY][NX] forward dir 2
-    CT *sr = sb;                                 // [NF][P][TY][NX] backward dir 1 (sb is dead by then)
-    CT *t1B = sb + NF * P * TY * NX, *t1D = t1B + E * PP;   // tables [elem][g][j]
+    CT *sa = yw + P * NXY;                       // [2][P][NY][NX]
+    CT *sh = G == 1 ? sa : sa + SA;              // [NF][PG][TY][TX]
+    CT *sq = G == 1 ? sa : sh + SH;              // [2][P][NY][NX]
+    CT *sb = sa + SAHQ;                          // [NF][PG][TY][NX]
+    CT *sr = sb;
+    CT *t1B = sb + SB, *t1D = t1B + E * PP;      // tables [elem][g][j]
     CT *t2B = t1D + E * PP, *t2D = t2B + E * PP;
-    CT *t3B = t2D + E * PP, *t3D = t3B + PP;
+    CT *t3Bb = t2D + E * PP, *t3Db = t3Bb + 2 * PP;   // direction-3 tables, [layer parity][g][j]
+    static_assert(NXY <= NT && PP <= NT, "one prefetched x value and table entry per thread");
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
     const int e1b = bx * E, e2b = by * E;
@@ -63,33 +132,21 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     const int Q0 = d0.Q, Q1 = d1.Q;
     const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
 
-    // coefficients of one layer for this column: when they are few (order 2
-    // stiffness, mass) all planes are held in registers and the next layer's
-    // are fetched during this one; otherwise they are read plane by plane in
-    // the pointwise stage, which keeps the registers low enough for more
-    // resident waves (measured faster from order 3 on)
-    constexpr bool PRE = P * NC <= 12;
-    // FP64 at order 4 and FP32 at order 3: the current layer's coefficients
-    // are held in registers at little or no cost in occupancy (at FP64 order
-    // 4 the LDS already limits the kernel to 3 waves per SIMD); they are
-    // loaded at the start of the layer and have the two forward stages to
-    // arrive.  Measured slower for the other orders.
-    constexpr bool LAYER = !PRE && (sizeof(CT) == sizeof(double) ? P == 4 : P == 3);
-    // Backward directions 1 and 2 in two steps (per-element sums, then sums
-    // over the elements sharing a function) where it pays: FP64 from order 3,
-    // FP32 from order 5 (measured).
-    constexpr bool TWOSTEP = sizeof(CT) == sizeof(double) ? P >= 3 : P >= 5;
-    constexpr int NCR = (PRE || LAYER) ? P : 1;
-    CT cur[NCR][NC], nxt[PRE ? NCR : 1][NC];
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
     auto load_plane = [&](int e3, int g3, CT *dst) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             dst[c] = active ? C[coef_index(3, NC, c, cq0, cq1, e3 * P + g3, Q0, Q1)] : CT(0);
     };
-    auto load_layer = [&](int e3, CT (*dst)[NC]) {
+    // coefficients of the planes of group grp of layer e3 (CMODE 1, 2)
+    constexpr int NCR = CMODE ? PG : 1;
+    CT cur[NCR][NC], nxt[CMODE == 2 ? NCR : 1][NC];
+    auto load_group = [&](int e3, int grp, CT (*dst)[NC]) {
 #pragma unroll
-        for (int g3 = 0; g3 < NCR; ++g3) load_plane(e3, g3, dst[g3]);
+        for (int gl = 0; gl < NCR; ++gl) {
+            const int g3 = grp * PG + gl;
+            if (g3 < P) load_plane(e3, g3, dst[gl]);
+        }
     };
     auto load_xrow = [&](int n3) {
         for (int idx = tid; idx < NXY; idx += NT) {
@@ -110,7 +167,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         }
     };
 
-    if (PRE) load_layer(e3a, cur);
+    if (CMODE == 2) load_group(e3a, 0, cur);
     for (int i = tid; i < E * PP; i += NT) {
         const int ea = e1b + i / PP, eb = e2b + i / PP;
         const int64_t sa1 = (int64_t)(ea < d0.K ? ea : 0) * PP + i % PP;   // in-bounds addresses
@@ -121,18 +178,44 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         t2D[i] = eb < d1.K ? (CT)d1.D[sb2] : CT(0);
     }
     for (int i = tid; i < P * NXY; i += NT) yw[i] = CT(0);
-    for (int r = 0; r < P - 1; ++r) load_xrow(e3a + r);
+    for (int r = 0; r < P; ++r) load_xrow(e3a + r);
+    if (tid < PP) {
+        t3Bb[(e3a & 1) * PP + tid] = (CT)d2.B[(int64_t)e3a * PP + tid];
+        t3Db[(e3a & 1) * PP + tid] = (CT)d2.D[(int64_t)e3a * PP + tid];
+    }
+    // the x row and the direction-3 tables of the next layer are loaded into
+    // registers at the start of a layer and stored to LDS once the forward
+    // direction-3 stage no longer reads the slot, so that no layer waits for
+    // a global load before its first stage
+    const int xlx = tid % NX, xly = tid / NX;
+    const bool xin = tid < NXY && e1b + xlx < d0.N && e2b + xly < d1.N;
+    const int64_t xoff = xin ? (e1b + xlx) + N0 * (e2b + xly) : 0;
+    __syncthreads();
 
     for (int e3 = e3a; e3 <= e3z; ++e3) {
-        // ---- new x row entering the window, tables of this layer, next coefficients
-        load_xrow(e3 + P - 1);
-        for (int i = tid; i < PP; i += NT) {
-            t3B[i] = (CT)d2.B[(int64_t)e3 * PP + i];
-            t3D[i] = (CT)d2.D[(int64_t)e3 * PP + i];
+        const CT *t3B = t3Bb + (e3 & 1) * PP, *t3D = t3Db + (e3 & 1) * PP;
+        const bool more = e3 < e3z;
+        double xn = 0.0, tnB = 0.0, tnD = 0.0;
+        if (more) {
+            if (xin) xn = x[xoff + N01 * (e3 + P)];
+            if (tid < PP) {
+                tnB = d2.B[(int64_t)(e3 + 1) * PP + tid];
+                tnD = d2.D[(int64_t)(e3 + 1) * PP + tid];
+            }
         }
-        if (PRE && e3 < e3z) load_layer(e3 + 1, nxt);
-        if (LAYER) load_layer(e3, cur);
-        __syncthreads();
+        // the first group's coefficients (CMODE 1) have the forward stages to
+        // arrive; with one group, CMODE 2 fetches the next layer's here, a
+        // whole layer ahead
+        if (CMODE == 1) load_group(e3, 0, cur);
+        if (CMODE == 2 && G == 1) {
+            if (e3 > e3a) {
+#pragma unroll
+                for (int gl = 0; gl < NCR; ++gl)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) cur[gl][c] = nxt[CMODE == 2 ? gl : 0][c];
+            }
+            if (more) load_group(e3 + 1, 0, nxt);
+        }
         // ---- forward, direction 3: a = B3 x, b = D3 x, every plane
         for (int idx = tid; idx < P * NXY; idx += NT) {
             const int g3 = idx / NXY, j = idx % NXY;
@@ -147,239 +230,312 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
             if (STIFF) sa[(P + g3) * NXY + j] = b;
         }
         __syncthreads();
-        // ---- forward, direction 2: B2 a (d1 and value), D2 a (d2), B2 b (d3)
-        for (int idx = tid; idx < P * TY * NX; idx += NT) {
-            const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
-            const int l2 = yy / P, h2 = yy % P;
-            CT vb = CT(0), vd = CT(0), wb = CT(0);
-#pragma unroll
-            for (int s = 0; s < P; ++s) {
-                const CT a = sa[g3 * NXY + (l2 + s) * NX + lx];
-                const CT bv = t2B[(l2 * P + h2) * P + s];
-                vb += bv * a;
-                if (STIFF) {
-                    vd += t2D[(l2 * P + h2) * P + s] * a;
-                    wb += bv * sa[(P + g3) * NXY + (l2 + s) * NX + lx];
-                }
-            }
-            sb[(0 * P + g3) * TY * NX + yy * NX + lx] = vb;
-            if (STIFF) {
-                sb[(1 * P + g3) * TY * NX + yy * NX + lx] = vd;
-                sb[(2 * P + g3) * TY * NX + yy * NX + lx] = wb;
+        // ---- the slot of x row e3 and the other table buffer are free now
+        if (more) {
+            if (tid < NXY) xw[((e3 + P) % P) * NXY + tid] = (CT)xn;
+            if (tid < PP) {
+                t3Bb[((e3 + 1) & 1) * PP + tid] = (CT)tnB;
+                t3Db[((e3 + 1) & 1) * PP + tid] = (CT)tnD;
             }
         }
-        __syncthreads();
-        // ---- forward, direction 1, and the pointwise coefficient, every plane
-        if (tid < TX * TY) {
-            const CT *b1 = t1B + (le1 * P + g1) * P, *db1 = t1D + (le1 * P + g1) * P;
-            constexpr int UNR = (PRE || LAYER) ? P : 1;   // planes unrolled (registers hold cur)
-#pragma unroll UNR
-            for (int g3 = 0; g3 < P; ++g3) {
-                CT cpl[NC];
-                if (!PRE && !LAYER) load_plane(e3, g3, cpl);
-                const CT *cg = (PRE || LAYER) ? cur[g3 < NCR ? g3 : 0] : cpl;
-                CT h[NF];
-                if (STIFF) {
-                    CT gr0 = CT(0), gr1 = CT(0), gr2 = CT(0);
+#pragma unroll 1
+        for (int grp = 0; grp < G; ++grp) {
+            const int g0 = grp * PG;
+            const int npl = (P - g0 < PG) ? P - g0 : PG;         // planes in this group
+            if (CMODE == 1 && grp > 0) load_group(e3, grp, cur);
+            if (CMODE == 2 && G > 1 && (grp > 0 || e3 > e3a)) {
 #pragma unroll
-                    for (int s = 0; s < P; ++s) {
-                        gr0 += db1[s] * sb[(0 * P + g3) * TY * NX + ty * NX + le1 + s];
-                        gr1 += b1[s] * sb[(1 * P + g3) * TY * NX + ty * NX + le1 + s];
-                        gr2 += b1[s] * sb[(2 * P + g3) * TY * NX + ty * NX + le1 + s];
-                    }
-                    const CT *c = cg;             // components 00 11 22 01 02 12
-                    h[0] = c[0] * gr0 + c[3] * gr1 + c[4] * gr2;
-                    h[NF > 1 ? 1 : 0] = c[3] * gr0 + c[1] * gr1 + c[5] * gr2;
-                    h[NF > 2 ? 2 : 0] = c[4] * gr0 + c[5] * gr1 + c[2] * gr2;
-                } else {
-                    CT u = CT(0);
+                for (int gl = 0; gl < NCR; ++gl)
 #pragma unroll
-                    for (int s = 0; s < P; ++s) u += b1[s] * sb[g3 * TY * NX + ty * NX + le1 + s];
-                    h[0] = cg[0] * u;
-                }
-#pragma unroll
-                for (int f = 0; f < NF; ++f) sh[(f * P + g3) * TY * TX + ty * TX + tx] = active ? h[f] : CT(0);
+                    for (int c = 0; c < NC; ++c) cur[gl][c] = nxt[CMODE == 2 ? gl : 0][c];
             }
-        }
-        __syncthreads();
-        // ---- backward, direction 1: D1^T h1, B1^T h2, B1^T h3 (mass: B1^T h)
-        if constexpr (TWOSTEP) {
-            // In two steps in place over sh.  First, per (plane, row, element l1), the
-            // p sums over the element's points, part[f][j] = sum_h T_f(l1, h, j)
-            // v[f][h], written over the element's own p values; then, per function
-            // column lx, the sum over the <= p elements that share it.
-            for (int idx = tid; idx < P * TY * E; idx += NT) {
-                const int l1 = idx % E, rest = idx / E;
-                const int yy = rest % TY, g3 = rest / TY;
-                const int col0 = (g3 * TY + yy) * TX + l1 * P;
-                CT v[NF][P];
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int h = 0; h < P; ++h) v[f][h] = sh[f * P * TY * TX + col0 + h];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const CT *T = (STIFF && f == 0) ? t1D : t1B;
-#pragma unroll
-                    for (int j = 0; j < P; ++j) {
-                        CT part = CT(0);
-#pragma unroll
-                        for (int h = 0; h < P; ++h) part += T[(l1 * P + h) * P + j] * v[f][h];
-                        sh[f * P * TY * TX + col0 + j] = part;
-                    }
-                }
-            }
-            __syncthreads();
-            for (int idx = tid; idx < P * TY * NX; idx += NT) {
-                const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
-                CT r[NF];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) r[f] = CT(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l1 = lx - j;                    // element whose local function j is lx
-                    if (l1 < 0 || l1 >= E) continue;
-                    const int col = (g3 * TY + yy) * TX + l1 * P + j;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) r[f] += sh[f * P * TY * TX + col];
-                }
-#pragma unroll
-                for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
-            }
-            __syncthreads();
-        } else {
-            // one item per (plane, row, function column), p^2 terms each
-            for (int idx = tid; idx < P * TY * NX; idx += NT) {
-                const int lx = idx % NX, yy = (idx / NX) % TY, g3 = idx / (NX * TY);
-                CT r[NF];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) r[f] = CT(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l1 = lx - j;                    // element whose local function j is lx
-                    if (l1 < 0 || l1 >= E) continue;
-#pragma unroll
-                    for (int h1 = 0; h1 < P; ++h1) {
-                        const CT bv = t1B[(l1 * P + h1) * P + j];
-                        const int col = (g3 * TY + yy) * TX + l1 * P + h1;
-                        if (STIFF) {
-                            r[0] += t1D[(l1 * P + h1) * P + j] * sh[0 * P * TY * TX + col];
-                            r[NF > 1 ? 1 : 0] += bv * sh[1 * P * TY * TX + col];
-                            r[NF > 2 ? 2 : 0] += bv * sh[2 * P * TY * TX + col];
-                        } else {
-                            r[0] += bv * sh[col];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int f = 0; f < NF; ++f) sr[(f * P + g3) * TY * NX + yy * NX + lx] = r[f];
-            }
-            __syncthreads();
-        }
-        // ---- backward, direction 2 into sq (the pointwise results in sa are
-        // dead once direction 1 has run)
-        CT *sq = sa;                                 // [2][P][NY][NX]
-        if constexpr (TWOSTEP) {
-            // In two steps, in place over sr: per (plane, element l2, column lx)
-            // the p sums over the element's points (sB into field 0, sD into
-            // field 1 of the element's own rows), then per function row the sum
-            // over the <= p elements that share it.
-            for (int idx = tid; idx < P * E * NX; idx += NT) {
-                const int lx = idx % NX, rest = idx / NX;
-                const int l2 = rest % E, g3 = rest / E;
-                const int row0 = (g3 * TY + l2 * P) * NX + lx;          // point h: row0 + h NX
-                CT v[NF][P];
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int h = 0; h < P; ++h) v[f][h] = sr[f * P * TY * NX + row0 + h * NX];
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    CT pB = CT(0), pD = CT(0);
-#pragma unroll
-                    for (int h = 0; h < P; ++h) {
-                        const CT bv = t2B[(l2 * P + h) * P + j];
-                        if (STIFF) {
-                            pB += bv * v[0][h] + t2D[(l2 * P + h) * P + j] * v[NF > 1 ? 1 : 0][h];
-                            pD += bv * v[NF > 2 ? 2 : 0][h];
-                        } else {
-                            pB += bv * v[0][h];
-                        }
-                    }
-                    sr[row0 + j * NX] = pB;
-                    if (STIFF) sr[1 * P * TY * NX + row0 + j * NX] = pD;
-                }
-            }
-            __syncthreads();
-            for (int idx = tid; idx < P * NXY; idx += NT) {
-                const int j2 = idx % NXY, g3 = idx / NXY;
-                const int lx = j2 % NX, ly = j2 / NX;
-                CT sB = CT(0), sD = CT(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l2 = ly - j;
-                    if (l2 < 0 || l2 >= E) continue;
-                    const int row = (g3 * TY + l2 * P + j) * NX + lx;
-                    sB += sr[row];
-                    if (STIFF) sD += sr[1 * P * TY * NX + row];
-                }
-                sq[g3 * NXY + j2] = sB;
-                if (STIFF) sq[(P + g3) * NXY + j2] = sD;
-            }
-            __syncthreads();
-        } else {
-            // one item per (plane, function column), p^2 terms each
-            for (int idx = tid; idx < P * NXY; idx += NT) {
-                const int j2 = idx % NXY, g3 = idx / NXY;
-                const int lx = j2 % NX, ly = j2 / NX;
-                CT sB = CT(0), sD = CT(0);
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l2 = ly - j;
-                    if (l2 < 0 || l2 >= E) continue;
-#pragma unroll
-                    for (int h2 = 0; h2 < P; ++h2) {
-                        const CT bv = t2B[(l2 * P + h2) * P + j];
-                        const int row = (g3 * TY + l2 * P + h2) * NX + lx;
-                        if (STIFF) {
-                            sB += bv * sr[0 * P * TY * NX + row] + t2D[(l2 * P + h2) * P + j] * sr[1 * P * TY * NX + row];
-                            sD += bv * sr[2 * P * TY * NX + row];
-                        } else {
-                            sB += bv * sr[row];
-                        }
-                    }
-                }
-                sq[g3 * NXY + j2] = sB;
-                if (STIFF) sq[(P + g3) * NXY + j2] = sD;
-            }
-            __syncthreads();
-        }
-        // ---- backward, direction 3 into the y window
-        for (int idx = tid; idx < NXY; idx += NT) {
-            CT acc[P];
-#pragma unroll
-            for (int s = 0; s < P; ++s) acc[s] = CT(0);
-#pragma unroll
-            for (int g3 = 0; g3 < P; ++g3) {
-                const CT sB = sq[g3 * NXY + idx], sD = STIFF ? sq[(P + g3) * NXY + idx] : CT(0);
+            // ---- forward, direction 2: B2 a (d1 and value), D2 a (d2), B2 b (d3)
+            for (int idx = tid; idx < npl * TY * NX; idx += NT) {
+                const int lx = idx % NX, yy = (idx / NX) % TY, gl = idx / (NX * TY);
+                const int g3 = g0 + gl;
+                const int l2 = yy / P, h2 = yy % P;
+                CT vb = CT(0), vd = CT(0), wb = CT(0);
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
-                    acc[s] += t3B[g3 * P + s] * sB;
-                    if (STIFF) acc[s] += t3D[g3 * P + s] * sD;
+                    const CT a = sa[g3 * NXY + (l2 + s) * NX + lx];
+                    const CT bv = t2B[(l2 * P + h2) * P + s];
+                    vb += bv * a;
+                    if (STIFF) {
+                        vd += t2D[(l2 * P + h2) * P + s] * a;
+                        wb += bv * sa[(P + g3) * NXY + (l2 + s) * NX + lx];
+                    }
+                }
+                sb[(0 * PG + gl) * TY * NX + yy * NX + lx] = vb;
+                if (STIFF) {
+                    sb[(1 * PG + gl) * TY * NX + yy * NX + lx] = vd;
+                    sb[(2 * PG + gl) * TY * NX + yy * NX + lx] = wb;
                 }
             }
+            __syncthreads();
+            // ---- forward, direction 1, and the pointwise coefficient, every plane of the group
+            if (tid < TX * TY) {
+                const CT *b1 = t1B + (le1 * P + g1) * P, *db1 = t1D + (le1 * P + g1) * P;
 #pragma unroll
-            for (int s = 0; s < P; ++s) yw[((e3 + s) % P) * NXY + idx] += acc[s];
+                for (int gl = 0; gl < PG; ++gl) {
+                    if (gl >= npl) break;
+                    CT cpl[NC];
+                    if (CMODE == 0) load_plane(e3, g0 + gl, cpl);
+                    const CT *cg = CMODE ? cur[CMODE ? gl : 0] : cpl;
+                    CT h[NF];
+                    if (STIFF) {
+                        CT gr0 = CT(0), gr1 = CT(0), gr2 = CT(0);
+#pragma unroll
+                        for (int s = 0; s < P; ++s) {
+                            gr0 += db1[s] * sb[(0 * PG + gl) * TY * NX + ty * NX + le1 + s];
+                            gr1 += b1[s] * sb[(1 * PG + gl) * TY * NX + ty * NX + le1 + s];
+                            gr2 += b1[s] * sb[(2 * PG + gl) * TY * NX + ty * NX + le1 + s];
+                        }
+                        const CT *c = cg;             // components 00 11 22 01 02 12
+                        h[0] = c[0] * gr0 + c[3] * gr1 + c[4] * gr2;
+                        h[NF > 1 ? 1 : 0] = c[3] * gr0 + c[1] * gr1 + c[5] * gr2;
+                        h[NF > 2 ? 2 : 0] = c[4] * gr0 + c[5] * gr1 + c[2] * gr2;
+                    } else {
+                        CT u = CT(0);
+#pragma unroll
+                        for (int s = 0; s < P; ++s) u += b1[s] * sb[gl * TY * NX + ty * NX + le1 + s];
+                        h[0] = cg[0] * u;
+                    }
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) sh[(f * PG + gl) * TY * TX + ty * TX + tx] = active ? h[f] : CT(0);
+                }
+            }
+            // the coefficients of the next group (or of the next layer's first
+            // group) are on their way during the backward stages
+            if (CMODE == 2 && G > 1) {
+                if (grp + 1 < G) load_group(e3, grp + 1, nxt);
+                else if (more) load_group(e3 + 1, 0, nxt);
+            }
+            __syncthreads();
+            // ---- backward, direction 1: D1^T h1, B1^T h2, B1^T h3 (mass: B1^T h)
+            if constexpr (TWOSTEP) {
+                // In two steps in place over sh.  First, per (plane, row, element l1),
+                // the p sums over the element's points, part[f][j] = sum_h
+                // T_f(l1, h, j) v[f][h], written over the element's own p values;
+                // then, per function column lx, the sum over the <= p elements
+                // that share it.
+                for (int idx = tid; idx < npl * TY * E; idx += NT) {
+                    const int l1 = idx % E, rest = idx / E;
+                    const int yy = rest % TY, gl = rest / TY;
+                    const int col0 = (gl * TY + yy) * TX + l1 * P;
+                    if constexpr (CF::UNRJ) {
+                        // every field's p values first, then all outputs
+                        CT v[NF][P];
+#pragma unroll
+                        for (int f = 0; f < NF; ++f)
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) v[f][hh] = sh[f * PG * TY * TX + col0 + hh];
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) {
+                            const CT *T = (STIFF && f == 0) ? t1D : t1B;
+#pragma unroll
+                            for (int j = 0; j < P; ++j) {
+                                CT part = CT(0);
+#pragma unroll
+                                for (int hh = 0; hh < P; ++hh) part += T[(l1 * P + hh) * P + j] * v[f][hh];
+                                sh[f * PG * TY * TX + col0 + j] = part;
+                            }
+                        }
+                    } else {
+                        // one field at a time, one output at a time: its p values are
+                        // read before any is overwritten, and only p table values are
+                        // live at once
+#pragma unroll 1
+                        for (int f = 0; f < NF; ++f) {
+                            const CT *T = (STIFF && f == 0) ? t1D : t1B;
+                            CT *col = sh + f * PG * TY * TX + col0;
+                            CT v[P];
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) v[hh] = col[hh];
+#pragma unroll 1
+                            for (int j = 0; j < P; ++j) {
+                                CT part = CT(0);
+#pragma unroll
+                                for (int hh = 0; hh < P; ++hh) part += T[(l1 * P + hh) * P + j] * v[hh];
+                                col[j] = part;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int idx = tid; idx < npl * TY * NX; idx += NT) {
+                    const int lx = idx % NX, yy = (idx / NX) % TY, gl = idx / (NX * TY);
+                    CT r[NF];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) r[f] = CT(0);
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const int l1 = lx - j;                    // element whose local function j is lx
+                        if (l1 < 0 || l1 >= E) continue;
+                        const int col = (gl * TY + yy) * TX + l1 * P + j;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) r[f] += sh[f * PG * TY * TX + col];
+                    }
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) sr[(f * PG + gl) * TY * NX + yy * NX + lx] = r[f];
+                }
+                __syncthreads();
+            } else {
+                // one item per (plane, row, function column), p^2 terms each
+                for (int idx = tid; idx < npl * TY * NX; idx += NT) {
+                    const int lx = idx % NX, yy = (idx / NX) % TY, gl = idx / (NX * TY);
+                    CT r[NF];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) r[f] = CT(0);
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const int l1 = lx - j;                    // element whose local function j is lx
+                        if (l1 < 0 || l1 >= E) continue;
+#pragma unroll
+                        for (int h1 = 0; h1 < P; ++h1) {
+                            const CT bv = t1B[(l1 * P + h1) * P + j];
+                            const int col = (gl * TY + yy) * TX + l1 * P + h1;
+                            if (STIFF) {
+                                r[0] += t1D[(l1 * P + h1) * P + j] * sh[0 * PG * TY * TX + col];
+                                r[NF > 1 ? 1 : 0] += bv * sh[1 * PG * TY * TX + col];
+                                r[NF > 2 ? 2 : 0] += bv * sh[2 * PG * TY * TX + col];
+                            } else {
+                                r[0] += bv * sh[col];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) sr[(f * PG + gl) * TY * NX + yy * NX + lx] = r[f];
+                }
+                __syncthreads();
+            }
+            // ---- backward, direction 2 into sq at the group's planes
+            if constexpr (TWOSTEP) {
+                // In two steps, in place over sr: per (plane, element l2, column lx)
+                // the p sums over the element's points (sB into field 0, sD into
+                // field 1 of the element's own rows), then per function row the sum
+                // over the <= p elements that share it.
+                for (int idx = tid; idx < npl * E * NX; idx += NT) {
+                    const int lx = idx % NX, rest = idx / NX;
+                    const int l2 = rest % E, gl = rest / E;
+                    const int row0 = (gl * TY + l2 * P) * NX + lx;          // point h: row0 + h NX
+                    if constexpr (CF::UNRJ) {
+                        CT v[NF][P];
+#pragma unroll
+                        for (int f = 0; f < NF; ++f)
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) v[f][hh] = sr[f * PG * TY * NX + row0 + hh * NX];
+#pragma unroll
+                        for (int j = 0; j < P; ++j) {
+                            CT pB = CT(0), pD = CT(0);
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) {
+                                const CT bv = t2B[(l2 * P + hh) * P + j];
+                                if (STIFF) {
+                                    pB += bv * v[0][hh] + t2D[(l2 * P + hh) * P + j] * v[NF > 1 ? 1 : 0][hh];
+                                    pD += bv * v[NF > 2 ? 2 : 0][hh];
+                                } else {
+                                    pB += bv * v[0][hh];
+                                }
+                            }
+                            sr[row0 + j * NX] = pB;
+                            if (STIFF) sr[1 * PG * TY * NX + row0 + j * NX] = pD;
+                        }
+                        continue;
+                    }
+                    // sB from fields 0 and 1 into field 0, then sD from field 2 into
+                    // field 1: each step reads its inputs before it overwrites them
+                    {
+                        CT v0[P], v1[P];
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh) {
+                            v0[hh] = sr[row0 + hh * NX];
+                            v1[hh] = STIFF ? sr[1 * PG * TY * NX + row0 + hh * NX] : CT(0);
+                        }
+#pragma unroll 1
+                        for (int j = 0; j < P; ++j) {
+                            CT pB = CT(0);
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) {
+                                pB += t2B[(l2 * P + hh) * P + j] * v0[hh];
+                                if (STIFF) pB += t2D[(l2 * P + hh) * P + j] * v1[hh];
+                            }
+                            sr[row0 + j * NX] = pB;
+                        }
+                    }
+                    if (STIFF) {
+                        CT v2[P];
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh) v2[hh] = sr[(NF - 1) * PG * TY * NX + row0 + hh * NX];
+#pragma unroll 1
+                        for (int j = 0; j < P; ++j) {
+                            CT pD = CT(0);
+#pragma unroll
+                            for (int hh = 0; hh < P; ++hh) pD += t2B[(l2 * P + hh) * P + j] * v2[hh];
+                            sr[1 * PG * TY * NX + row0 + j * NX] = pD;
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int idx = tid; idx < npl * NXY; idx += NT) {
+                    const int j2 = idx % NXY, gl = idx / NXY;
+                    const int g3 = g0 + gl;
+                    const int lx = j2 % NX, ly = j2 / NX;
+                    CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const int l2 = ly - j;
+                        if (l2 < 0 || l2 >= E) continue;
+                        const int row = (gl * TY + l2 * P + j) * NX + lx;
+                        sB += sr[row];
+                        if (STIFF) sD += sr[1 * PG * TY * NX + row];
+                    }
+                    sq[g3 * NXY + j2] = sB;
+                    if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+                }
+            } else {
+                // one item per (plane, function column), p^2 terms each
+                for (int idx = tid; idx < npl * NXY; idx += NT) {
+                    const int j2 = idx % NXY, gl = idx / NXY;
+                    const int g3 = g0 + gl;
+                    const int lx = j2 % NX, ly = j2 / NX;
+                    CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const int l2 = ly - j;
+                        if (l2 < 0 || l2 >= E) continue;
+#pragma unroll
+                        for (int h2 = 0; h2 < P; ++h2) {
+                            const CT bv = t2B[(l2 * P + h2) * P + j];
+                            const int row = (gl * TY + l2 * P + h2) * NX + lx;
+                            if (STIFF) {
+                                sB += bv * sr[0 * PG * TY * NX + row] +
+                                      t2D[(l2 * P + h2) * P + j] * sr[1 * PG * TY * NX + row];
+                                sD += bv * sr[2 * PG * TY * NX + row];
+                            } else {
+                                sB += bv * sr[row];
+                            }
+                        }
+                    }
+                    sq[g3 * NXY + j2] = sB;
+                    if (STIFF) sq[(P + g3) * NXY + j2] = sD;
+                }
+            }
+            __syncthreads();
+        }
+        // ---- backward, direction 3 into the y window, one item per (row s, column)
+        for (int idx = tid; idx < P * NXY; idx += NT) {
+            const int s3 = idx / NXY, j = idx % NXY;
+            CT acc = CT(0);
+#pragma unroll
+            for (int g3 = 0; g3 < P; ++g3) {
+                acc += t3B[g3 * P + s3] * sq[g3 * NXY + j];
+                if (STIFF) acc += t3D[g3 * P + s3] * sq[(P + g3) * NXY + j];
+            }
+            yw[((e3 + s3) % P) * NXY + j] += acc;
         }
         __syncthreads();
         // ---- row e3 is complete for this box
         flush_yrow(e3);
-        if (PRE && e3 < e3z) {
-#pragma unroll
-            for (int g3 = 0; g3 < P; ++g3)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) cur[g3 < NCR ? g3 : 0][c] = nxt[PRE && g3 < NCR ? g3 : 0][c];
-        }
     }
     __syncthreads();
     for (int r = 1; r < P; ++r) flush_yrow(e3z + r);
@@ -389,16 +545,21 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
 // atomics into y.
 
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(STile<P>::NT) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
+__global__ __launch_bounds__(STile<P>::NT, (ApplyCfg<P, STIFF, CT>::W)) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
                                                               const double *__restrict__ x, double *__restrict__ y,
                                                               int LZ)
 {
-    apply3d_block<P, STIFF, CT>(pv, C, x, y, LZ, blockIdx.x, blockIdx.y, blockIdx.z);
+    // neighbouring tiles in direction 1 share the cache lines at the ends of
+    // their coefficient rows (a tile row is TX values, not a whole number of
+    // 128-byte lines): on one XCD those lines are fetched once
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    if (ApplyCfg<P, STIFF, CT>::XCD) xcd_tile(bx, by, bz);
+    apply3d_block<P, STIFF, CT>(pv, C, x, y, LZ, bx, by, bz);
 }
 
 // Persistent form over the concatenated per-patch grids of a batch.
 template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(STile<P>::NT) void apply3d_persistent(TaskList tl)
+__global__ __launch_bounds__(STile<P>::NT, (ApplyCfg<P, STIFF, CT>::W)) void apply3d_persistent(TaskList tl)
 {
     for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
         const int t = task_of(tl.off, tl.ntask, it);
@@ -482,10 +643,13 @@ template <int P, bool STIFF, typename CT>
 static size_t apply3d_lds()
 {
     using TL = STile<P>;
+    using CF = ApplyCfg<P, STIFF, CT>;
     constexpr int NF = STIFF ? 3 : 1;
     constexpr int NXY = TL::NX * TL::NY;
-    constexpr int SA = (2 * P * NXY > NF * P * TL::TY * TL::TX) ? 2 * P * NXY : NF * P * TL::TY * TL::TX;
-    return sizeof(CT) * (size_t)(2 * P * NXY + SA + NF * P * TL::TY * TL::NX + 4 * TL::E * P * P + 2 * P * P);
+    constexpr int PG = (P + CF::G - 1) / CF::G;
+    constexpr int SA = 2 * P * NXY, SH = NF * PG * TL::TY * TL::TX, SB = NF * PG * TL::TY * TL::NX;
+    constexpr int SAHQ = CF::G == 1 ? (SA > SH ? SA : SH) : 2 * SA + SH;
+    return sizeof(CT) * (size_t)(2 * P * NXY + SAHQ + SB + 4 * TL::E * P * P + 4 * P * P);
 }
 
 template <int P> static int apply_tile_elems() { return STile<P>::E; }

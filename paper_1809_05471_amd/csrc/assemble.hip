@@ -819,22 +819,6 @@ __device__ __forceinline__ void asm3_block(const PatchView &pv, const CT *__rest
     }
 }
 
-// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each with its
-// own L2.  Give every XCD a contiguous range of tiles instead, so that the
-// blocks of neighbouring rows m2, which write parts of the same CSR rows
-// (entries and mirrors), share one L2 and their partial lines merge there.
-__device__ __forceinline__ void xcd_tile(int &bx, int &by, int &bz)
-{
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int nb = gx * gy * gridDim.z;
-    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const int q = nb / 8, r = nb % 8, x = b % 8;
-    const int t = x * q + min(x, r) + b / 8;
-    bx = t % gx;
-    by = (t / gx) % gy;
-    bz = t / (gx * gy);
-}
-
 template <int P, bool STIFF, typename CT>
 __global__ __launch_bounds__(256) void asm3_kernel(PatchView pv, const CT *__restrict__ A2, double *__restrict__ vals,
                                                    int s0, int s1, int L, int seg0)

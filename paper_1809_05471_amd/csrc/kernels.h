@@ -91,6 +91,23 @@ __device__ __forceinline__ int task_of(const int64_t *off, int ntask, int64_t it
 // device, once per (device, kernel); thread safe.  Needed above 64 KiB.
 hipError_t allow_dynamic_lds(const void *fn, size_t bytes);
 
+// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with
+// its own L2.  xcd_tile gives every XCD a contiguous range of tiles instead
+// (direction 1 fastest), so that neighbouring tiles, which share cache lines
+// of their inputs or outputs, run on one XCD at about the same time and meet
+// in its L2.
+__device__ __forceinline__ void xcd_tile(int &bx, int &by, int &bz)
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int nb = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    const int t = x * q + min(x, r) + b / 8;
+    bx = t % gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+}
+
 hipError_t launch_geometry(const PatchView &pv, const GeomOut &out, hipStream_t s);
 hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
                           int64_t col_base, int64_t nnz_base, hipStream_t s);
