@@ -93,9 +93,13 @@ def apply_flops(K, p, op):
     return 2 * fwd + 2 * Q[0] * Q[1] * Q[2]
 
 
-def coef_bytes_per_point(prec_name, op="stiff"):
-    """Stored bytes of the folded coefficient tensor per quadrature point."""
+def coef_bytes_per_point(prec_name, op="stiff", p=6):
+    """Stored bytes of the folded coefficient tensor per quadrature point (FP16
+    split: 2 bytes per component plus an FP32 reference and scale per element
+    and component, shared by its p^3 points)."""
     nc = 6 if op == "stiff" else 1
+    if prec_name == "fp16":
+        return nc * (2 + 8 / p ** 3)
     return nc * {"fp64": 8, "fp32": 4, "bf16": 4}[prec_name]
 
 
@@ -118,7 +122,7 @@ def parse():
                     help="large: d=3 128^3 order 6, geometry + pattern + assembly + 100 applies per step (the "
                          "headline line); single: 48^3 order 4 with one apply; sweep: matrix-free apply at "
                          "N = 126^3 for orders 2..9; batched: 512 patches")
-    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16"], default=None,
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="precision of the timed step (default fp64; sweep and batched: see their help)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="steps timed per reduced-precision mode after the headline (0: skip)")
@@ -188,7 +192,12 @@ def run_patch(args):
     K, p = ((128, 128, 128), 6) if large else ((48, 48, 48), 4)
     applies = args.applies if args.applies is not None else (100 if large else 1)
     head_prec = args.prec or "fp64"
-    precs = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "bf16": sf.SF_BF16_SPLIT}
+    precs = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "bf16": sf.SF_BF16_SPLIT, "fp16": sf.SF_FP16_SPLIT}
+    # precision of (geometry step, assembly, applies) per mode: BF16 split is
+    # a mode of the assembly and FP16 split a storage of the apply, so those
+    # steps take FP32 for the other stage
+    plan = {"fp64": ("fp64", "fp64", "fp64"), "fp32": ("fp32", "fp32", "fp32"),
+            "bf16": ("bf16", "bf16", "fp32"), "fp16": ("fp16", "fp32", "fp16")}
     w = inputs.workload_3d(K, p)
     stream = torch.cuda.current_stream()
     ctx = sf.sf_ctx_create(0, stream.cuda_stream)
@@ -203,22 +212,23 @@ def run_patch(args):
     x = torch.as_tensor(w["x"]).cuda()
     y = torch.empty(N, dtype=torch.float64, device="cuda")
 
-    def step(prec, ev):
+    def step(mode, ev):
+        pg, pa, py = (precs[m] for m in plan[mode])
         if ev:
             ev[0].record(stream)
         # geometry step queued without a host round trip; its det J test is
         # read back once, after the timed steps (sf_patch_geometry_check)
-        sf.sf_patch_prepare_async(ctx, h, sf.SF_STIFF, prec)
+        sf.sf_patch_prepare_async(ctx, h, sf.SF_STIFF, pg)
         if ev:
             ev[1].record(stream)
         sf.sf_csr_pattern(ctx, h, rp, ci)
         if ev:
             ev[2].record(stream)
-        sf.sf_assemble(ctx, h, sf.SF_STIFF, prec, val_stiff=vals)
+        sf.sf_assemble(ctx, h, sf.SF_STIFF, pa, val_stiff=vals)
         if ev:
             ev[3].record(stream)
         for _ in range(applies):
-            sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
+            sf.sf_apply(ctx, h, sf.SF_STIFF, py, x, y)
         if ev:
             ev[4].record(stream)
 
@@ -248,7 +258,7 @@ def run_patch(args):
             o += len(sg)
         return out, y.cpu().numpy()[rows]
 
-    ms_step, (geom_ms, pat_ms, asm_ms, app_ms) = timed(precs[head_prec], args.steps, args.warmup)
+    ms_step, (geom_ms, pat_ms, asm_ms, app_ms) = timed(head_prec, args.steps, args.warmup)
     app_ms /= applies
     # sampled rows of every mode's results, for the error check against the oracle
     got = {}
@@ -262,29 +272,29 @@ def run_patch(args):
     # reduced-precision modes of the same step ("mixed vs FP64")
     modes = {}
     if args.mixed_steps > 0:
-        for name in ("fp64", "fp32", "bf16"):
+        for name in ("fp64", "fp32", "bf16", "fp16"):
             if name == head_prec:
                 continue
             try:
-                ms, (g_ms, p_ms, a_ms, y_ms) = timed(precs[name], args.mixed_steps, 1)
+                ms, (g_ms, p_ms, a_ms, y_ms) = timed(name, args.mixed_steps, 1)
             except sf.SfError as e:          # a mode the library does not build
                 modes[name] = {"status": str(e)}
                 continue
-            modes[name] = {"ms_per_step": ms, "value_gnnz_s": nnz / (ms * 1e-3) / 1e9,
+            modes[name] = {"precision_geometry_assembly_apply": list(plan[name]),
+                           "ms_per_step": ms, "value_gnnz_s": nnz / (ms * 1e-3) / 1e9,
                            "stages_ms": {"geometry": g_ms, "pattern": p_ms, "assembly": a_ms,
                                          "apply": y_ms / applies},
                            "assembly_gnnz_s": nnz / (a_ms * 1e-3) / 1e9,
                            "apply_gdof_s": N / (y_ms / applies * 1e-3) / 1e9,
-                           "apply_hbm_frac": (Q * coef_bytes_per_point(name) + 16 * N)
+                           "apply_hbm_frac": (Q * coef_bytes_per_point(plan[name][2], p=p) + 16 * N)
                            / (y_ms / applies * 1e-3) / 1e9 / PEAK_HBM_GBS}
             if oracle_rows is not None:
                 got[name] = device_rows(oracle_rows)
 
     fl_asm = assembly_flops(K, p, "stiff")
     fl_app = apply_flops(K, p, "stiff")
-    c_bytes = Q * coef_bytes_per_point(head_prec)
-    asm_bytes = c_bytes + nnz * 8
-    app_bytes = c_bytes + 2 * N * 8
+    asm_bytes = Q * coef_bytes_per_point(plan[head_prec][1], p=p) + nnz * 8
+    app_bytes = Q * coef_bytes_per_point(plan[head_prec][2], p=p) + 2 * N * 8
     asm_tflops = fl_asm / (asm_ms * 1e-3) / 1e12
     asm_peak = PEAK_FP64_TFLOPS if head_prec == "fp64" else PEAK_FP32_TFLOPS
     tag = "d3_128_p6" if large else "d3_48_p4"
@@ -312,7 +322,7 @@ def run_patch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16x3+f32"}[head_prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16x3+f32", "fp16": "f16split+f32"}[head_prec],
         "data": "synthetic",
         "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_perturbed_stiffness_geometry_pattern_assembly_"
                                f"plus_{applies}_applies",
@@ -400,7 +410,8 @@ def cpu_leg(P, w, p, K, N, nnz, applies, rows, got, head_prec, modes):
 
 
 def _prec_list(args, sf):
-    return [sf.SF_FP64, sf.SF_FP32] if args.prec is None else [sf.SF_FP64 if args.prec == "fp64" else sf.SF_FP32]
+    allp = {"fp64": sf.SF_FP64, "fp32": sf.SF_FP32, "fp16": sf.SF_FP16_SPLIT}
+    return list(allp.items()) if args.prec is None else [(args.prec, allp[args.prec])]
 
 
 def run_sweep(args):
@@ -420,7 +431,7 @@ def run_sweep(args):
         sf.sf_patch_set_coef(ctx, h, sf.SF_STIFF, sf.SF_COEF_SINPROD, 0.5)
         x = torch.as_tensor(w["x"]).cuda()
         y = torch.empty(N, dtype=torch.float64, device="cuda")
-        for prec in _prec_list(args, sf):
+        for name, prec in _prec_list(args, sf):
             sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, prec)
             for _ in range(args.warmup):
                 sf.sf_apply(ctx, h, sf.SF_STIFF, prec, x, y)
@@ -431,11 +442,10 @@ def run_sweep(args):
             e1.record(stream)
             e1.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
-            esz = 8 if prec == sf.SF_FP64 else 4
-            byts = 6 * Q * esz + 16 * N
+            byts = Q * coef_bytes_per_point(name, p=p) + 16 * N
             print(json.dumps({
                 "metric": "matrix-free apply GDoF/s", "value": N / (ms * 1e-3) / 1e9, "unit": "GDoF/s",
-                "ms": ms, "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+                "ms": ms, "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16split+f32"}[name],
                 "config": {"workload": f"d3_{K[0]}^3_p{p}_stiffness_apply", "order": p, "ndof": N, "nquad": Q},
                 "roofline": {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,

@@ -66,15 +66,22 @@ typedef enum {
 typedef enum {
     SF_FP64 = 0,           /* coefficient tensor and contractions in FP64 */
     SF_FP32 = 1,           /* coefficient tensor and contractions in FP32, FP64 output */
-    SF_BF16_SPLIT = 2,     /* FP32 coefficient tensor and first contraction level;
-                              the second level of the d = 3 assembly on bf16 matrix
+    SF_BF16_SPLIT = 2,     /* assembly only: FP32 coefficient tensor and first contraction
+                              level; the second level of the d = 3 assembly on bf16 matrix
                               cores, every operand split x = hi + lo (bf16) and the
                               products hi*hi + hi*lo + lo*hi accumulated in FP32; the
                               last level and the values in FP64 (measured error
-                              < 1e-4 of max |A|).  The apply and d <= 2 run FP32. */
-    SF_FP16_SPLIT = 3      /* not built (SF_EUNSUPPORTED): the second-level operands
-                              fall below the FP16 normal range, where the lo parts
-                              would be lost without per-block scaling */
+                              < 5e-6 of max |A|); d <= 2 run FP32.  sf_apply and
+                              sf_batch_apply return SF_EUNSUPPORTED. */
+    SF_FP16_SPLIT = 3      /* matrix-free apply only (d = 3): the folded coefficient
+                              tensor stored split, per element and component an FP32
+                              reference r and scale s, per quadrature point an FP16
+                              residual h, C = w (r + s h) with w the product of the
+                              point's Gauss weights (2 bytes per component instead of
+                              8); contractions in FP32.  Each stored coefficient is
+                              within 2^-12 s w of the FP32 one.  sf_patch_prepare at
+                              this precision also prepares SF_FP32; the assembly
+                              entry points return SF_EUNSUPPORTED. */
 } sf_precision;
 
 /* operator bit flags */

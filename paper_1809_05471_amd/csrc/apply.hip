@@ -15,13 +15,17 @@
 // costs no occupancy).  LZ is tuned per patch by the caller.  Partial y rows
 // leave the window through FP64 atomics (the accumulation of eq.
 // (loc-basis-change)), because boxes share functions.
+#include <hip/hip_fp16.h>
+
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace sfiga {
 
 template <int P>
 struct STile {
-    static constexpr int E = (16 + P - 1) / P;                 // elements per direction
+    static constexpr int E = apply_tile_elems(P);              // elements per direction
     static constexpr int TX = E * P, TY = E * P;               // quadrature columns
     static constexpr int NX = E + P - 1, NY = E + P - 1;       // functions
     static constexpr int NT = (TX * TY + 63) / 64 * 64;
@@ -62,8 +66,10 @@ struct ApplyShape {
     int G, CMODE, TWOSTEP, UNRJ, W, XCD;
 };
 
-constexpr ApplyShape apply_shape(int P, bool f64, bool stiff)
+// storage: 0 FP64, 1 FP32, 2 FP16 split
+constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
 {
+    const bool f64 = storage == 0;
     // BEGIN SHAPES
     if (!stiff || P == 2) return ApplyShape{1, 2, f64 ? P >= 3 : P >= 5, 1, 1, P == 2 || (!f64 && P <= 4)};
     if (f64) {
@@ -71,14 +77,16 @@ constexpr ApplyShape apply_shape(int P, bool f64, bool stiff)
         if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
         return ApplyShape{1, 0, 1, 0, 1, 0};
     }
+    if (storage == 2) return ApplyShape{1, P == 2 ? 2 : (P == 8 ? 1 : 0), P >= 5, 1, 1, P <= 4};
     if (P == 4) return ApplyShape{1, 0, 0, 1, 1, 1};
     return ApplyShape{1, 1, P >= 5, 1, 1, P <= 4};
     // END SHAPES
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CS>
 struct ApplyCfg {
-    static constexpr ApplyShape S = apply_shape(P, sizeof(CT) == sizeof(double), STIFF);
+    static constexpr ApplyShape S =
+        apply_shape(P, sizeof(CS) == sizeof(double) ? 0 : (sizeof(CS) == sizeof(float) ? 1 : 2), STIFF);
     static constexpr int G = S.G;
     static constexpr int CMODE = S.CMODE;
     static constexpr bool TWOSTEP = S.TWOSTEP != 0;
@@ -87,13 +95,23 @@ struct ApplyCfg {
     static constexpr bool XCD = S.XCD != 0;
 };
 
-template <int P, bool STIFF, typename CT>
-__device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__restrict__ C,
-                                              const double *__restrict__ x, double *__restrict__ y, int LZ, int bx,
-                                              int by, int bz)
+// Storage of the coefficient tensor: double or float (computed in that type),
+// or __half in the FP16-split form (computed in float): per element and
+// component a reference r and a scale s (FP32, `rs`), per point an FP16
+// residual h, with C = w (r + s h) where w is the product of the point's
+// Gauss weights.
+template <typename CS> struct ComputeOf { using T = CS; };
+template <> struct ComputeOf<__half> { using T = float; };
+
+template <int P, bool STIFF, typename CS>
+__device__ __forceinline__ void apply3d_block(const PatchView &pv, const CS *__restrict__ C,
+                                              const float *__restrict__ rs, const double *__restrict__ x,
+                                              double *__restrict__ y, int LZ, int bx, int by, int bz)
 {
+    using CT = typename ComputeOf<CS>::T;
+    constexpr bool SPLIT = !std::is_same<CS, CT>::value;
     using TL = STile<P>;
-    using CF = ApplyCfg<P, STIFF, CT>;
+    using CF = ApplyCfg<P, STIFF, CS>;
     constexpr int E = TL::E, NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
     constexpr int NF = STIFF ? 3 : 1;      // gradient components or value
     constexpr int NC = STIFF ? 6 : 1;      // coefficient components
@@ -119,6 +137,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     CT *t1B = sb + SB, *t1D = t1B + E * PP;      // tables [elem][g][j]
     CT *t2B = t1D + E * PP, *t2D = t2B + E * PP;
     CT *t3Bb = t2D + E * PP, *t3Db = t3Bb + 2 * PP;   // direction-3 tables, [layer parity][g][j]
+    CT *t3Wb = t3Db + 2 * PP;                         // direction-3 weights, [layer parity][g] (FP16 split)
     static_assert(NXY <= NT && PP <= NT, "one prefetched x value and table entry per thread");
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
@@ -133,15 +152,41 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
 
     const int cq0 = active ? (e1b + le1) * P + g1 : 0, cq1 = active ? (e2b + le2) * P + g2 : 0;
-    auto load_plane = [&](int e3, int g3, CT *dst) {
+    // stored values are kept raw in registers and converted where they are
+    // used, so that a prefetch never waits for its loads
+    // FP16 split: the tile's plane of one component is one contiguous block
+    // (split_index), read by the workgroup's threads in order
+    const int64_t tile0 = SPLIT ? split_index(NC, 0, e1b * P, e2b * P, 0, P, d0.K, d1.K) : 0;
+    const int64_t plane_stride = SPLIT ? split_index(NC, 1, 0, 0, 0, P, d0.K, d1.K) : 0;
+    auto load_plane = [&](int e3, int g3, CS *dst) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            dst[c] = active ? C[coef_index(3, NC, c, cq0, cq1, e3 * P + g3, Q0, Q1)] : CT(0);
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (SPLIT)
+                dst[c] = active ? C[tile0 + ((int64_t)(e3 * P + g3) * NC + c) * plane_stride + tid] : CS(0);
+            else
+                dst[c] = active ? C[coef_index(3, NC, c, cq0, cq1, e3 * P + g3, Q0, Q1)] : CS(0);
+        }
+    };
+    // FP16 split: the element's reference and scale of the current layer, and
+    // the weights of the thread's column in directions 1 and 2
+    CT rsr[SPLIT ? 2 * NC : 1];
+    const CT w12 = SPLIT && active ? (CT)(d0.W[cq0] * d1.W[cq1]) : CT(0);
+    const int64_t rs_col = SPLIT && active ? ((int64_t)(e2b + le2) * d0.K + e1b + le1) * 2 * NC : 0;
+    auto load_rs = [&](int e3) {
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int k = 0; k < 2 * NC; ++k)
+                rsr[k] = active ? rs[(int64_t)e3 * d1.K * d0.K * 2 * NC + rs_col + k] : CT(0);
+        }
+    };
+    auto coef = [&](CS raw, int c, CT w3v) -> CT {
+        if constexpr (SPLIT) return w12 * w3v * (rsr[2 * c] + rsr[2 * c + 1] * __half2float(raw));
+        else return (CT)raw;
     };
     // coefficients of the planes of group grp of layer e3 (CMODE 1, 2)
     constexpr int NCR = CMODE ? PG : 1;
-    CT cur[NCR][NC], nxt[CMODE == 2 ? NCR : 1][NC];
-    auto load_group = [&](int e3, int grp, CT (*dst)[NC]) {
+    CS cur[NCR][NC], nxt[CMODE == 2 ? NCR : 1][NC];
+    auto load_group = [&](int e3, int grp, CS (*dst)[NC]) {
 #pragma unroll
         for (int gl = 0; gl < NCR; ++gl) {
             const int g3 = grp * PG + gl;
@@ -183,6 +228,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
         t3Bb[(e3a & 1) * PP + tid] = (CT)d2.B[(int64_t)e3a * PP + tid];
         t3Db[(e3a & 1) * PP + tid] = (CT)d2.D[(int64_t)e3a * PP + tid];
     }
+    if (SPLIT && tid < P) t3Wb[(e3a & 1) * P + tid] = (CT)d2.W[(int64_t)e3a * P + tid];
     // the x row and the direction-3 tables of the next layer are loaded into
     // registers at the start of a layer and stored to LDS once the forward
     // direction-3 stage no longer reads the slot, so that no layer waits for
@@ -193,16 +239,18 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
     __syncthreads();
 
     for (int e3 = e3a; e3 <= e3z; ++e3) {
-        const CT *t3B = t3Bb + (e3 & 1) * PP, *t3D = t3Db + (e3 & 1) * PP;
+        const CT *t3B = t3Bb + (e3 & 1) * PP, *t3D = t3Db + (e3 & 1) * PP, *t3W = t3Wb + (e3 & 1) * P;
         const bool more = e3 < e3z;
-        double xn = 0.0, tnB = 0.0, tnD = 0.0;
+        double xn = 0.0, tnB = 0.0, tnD = 0.0, tnW = 0.0;
         if (more) {
             if (xin) xn = x[xoff + N01 * (e3 + P)];
             if (tid < PP) {
                 tnB = d2.B[(int64_t)(e3 + 1) * PP + tid];
                 tnD = d2.D[(int64_t)(e3 + 1) * PP + tid];
             }
+            if (SPLIT && tid < P) tnW = d2.W[(int64_t)(e3 + 1) * P + tid];
         }
+        load_rs(e3);
         // the first group's coefficients (CMODE 1) have the forward stages to
         // arrive; with one group, CMODE 2 fetches the next layer's here, a
         // whole layer ahead
@@ -237,6 +285,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
                 t3Bb[((e3 + 1) & 1) * PP + tid] = (CT)tnB;
                 t3Db[((e3 + 1) & 1) * PP + tid] = (CT)tnD;
             }
+            if (SPLIT && tid < P) t3Wb[((e3 + 1) & 1) * P + tid] = (CT)tnW;
         }
 #pragma unroll 1
         for (int grp = 0; grp < G; ++grp) {
@@ -278,9 +327,13 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
 #pragma unroll
                 for (int gl = 0; gl < PG; ++gl) {
                     if (gl >= npl) break;
-                    CT cpl[NC];
+                    CS cpl[NC];
                     if (CMODE == 0) load_plane(e3, g0 + gl, cpl);
-                    const CT *cg = CMODE ? cur[CMODE ? gl : 0] : cpl;
+                    const CS *cr = CMODE ? cur[CMODE ? gl : 0] : cpl;
+                    const CT w3v = SPLIT ? t3W[g0 + gl] : CT(0);
+                    CT cg[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) cg[c] = coef(cr[c], c, w3v);
                     CT h[NF];
                     if (STIFF) {
                         CT gr0 = CT(0), gr1 = CT(0), gr2 = CT(0);
@@ -544,22 +597,25 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CT *__r
 // d = 1, 2: one thread per element, element-local sum factorization,
 // atomics into y.
 
-template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(STile<P>::NT, (ApplyCfg<P, STIFF, CT>::W)) void apply3d_kernel(PatchView pv, const CT *__restrict__ C,
-                                                              const double *__restrict__ x, double *__restrict__ y,
-                                                              int LZ)
+template <int P, bool STIFF, typename CS>
+using ApplyCfgS = ApplyCfg<P, STIFF, CS>;
+
+template <int P, bool STIFF, typename CS>
+__global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void apply3d_kernel(
+    PatchView pv, const CS *__restrict__ C, const float *__restrict__ rs, const double *__restrict__ x,
+    double *__restrict__ y, int LZ)
 {
     // neighbouring tiles in direction 1 share the cache lines at the ends of
     // their coefficient rows (a tile row is TX values, not a whole number of
     // 128-byte lines): on one XCD those lines are fetched once
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    if (ApplyCfg<P, STIFF, CT>::XCD) xcd_tile(bx, by, bz);
-    apply3d_block<P, STIFF, CT>(pv, C, x, y, LZ, bx, by, bz);
+    if (ApplyCfgS<P, STIFF, CS>::XCD) xcd_tile(bx, by, bz);
+    apply3d_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
 }
 
 // Persistent form over the concatenated per-patch grids of a batch.
-template <int P, bool STIFF, typename CT>
-__global__ __launch_bounds__(STile<P>::NT, (ApplyCfg<P, STIFF, CT>::W)) void apply3d_persistent(TaskList tl)
+template <int P, bool STIFF, typename CS>
+__global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void apply3d_persistent(TaskList tl)
 {
     for (int64_t it = blockIdx.x; it < tl.nitems; it += gridDim.x) {
         const int t = task_of(tl.off, tl.ntask, it);
@@ -567,7 +623,8 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfg<P, STIFF, CT>::W)) void app
         const int64_t l = it - tl.off[t];
         const int bx = (int)(l % T.gx);
         const int64_t r = l / T.gx;
-        apply3d_block<P, STIFF, CT>(T.pv, (const CT *)T.C, T.x, T.out, T.arg, bx, (int)(r % T.gy), (int)(r / T.gy));
+        apply3d_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
+                                    (int)(r / T.gy));
         __syncthreads();   // LDS of the next block
     }
 }
@@ -639,34 +696,23 @@ __global__ void apply_small_kernel(PatchView pv, const CT *__restrict__ C, const
         for (int s0 = 0; s0 < P; ++s0) atomicAdd(&y[(e0 + s0) + (int64_t)d0.N * (e1 + s1)], yl[s1][s0]);
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CS>
 static size_t apply3d_lds()
 {
+    using CT = typename ComputeOf<CS>::T;
     using TL = STile<P>;
-    using CF = ApplyCfg<P, STIFF, CT>;
+    using CF = ApplyCfg<P, STIFF, CS>;
     constexpr int NF = STIFF ? 3 : 1;
     constexpr int NXY = TL::NX * TL::NY;
     constexpr int PG = (P + CF::G - 1) / CF::G;
     constexpr int SA = 2 * P * NXY, SH = NF * PG * TL::TY * TL::TX, SB = NF * PG * TL::TY * TL::NX;
     constexpr int SAHQ = CF::G == 1 ? (SA > SH ? SA : SH) : 2 * SA + SH;
-    return sizeof(CT) * (size_t)(2 * P * NXY + SAHQ + SB + 4 * TL::E * P * P + 4 * P * P);
+    return sizeof(CT) * (size_t)(2 * P * NXY + SAHQ + SB + 4 * TL::E * P * P + 4 * P * P + 2 * P);
 }
-
-template <int P> static int apply_tile_elems() { return STile<P>::E; }
 
 void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &LZ)
 {
-    int E = 0;
-    switch (pv.P) {
-    case 2: E = apply_tile_elems<2>(); break;
-    case 3: E = apply_tile_elems<3>(); break;
-    case 4: E = apply_tile_elems<4>(); break;
-    case 5: E = apply_tile_elems<5>(); break;
-    case 6: E = apply_tile_elems<6>(); break;
-    case 7: E = apply_tile_elems<7>(); break;
-    case 8: E = apply_tile_elems<8>(); break;
-    default: E = apply_tile_elems<9>(); break;
-    }
+    const int E = apply_tile_elems(pv.P);
     gx = (pv.dir[0].K + E - 1) / E;
     gy = (pv.dir[1].K + E - 1) / E;
     if (lz <= 0) {
@@ -679,46 +725,58 @@ void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &L
     gz = (pv.dir[2].K + LZ - 1) / LZ;
 }
 
-template <int P, bool STIFF, typename CT>
-static hipError_t launch_apply_t(const PatchView &pv, const CT *C, const double *x, double *y, hipStream_t s, int lz)
+template <int P, bool STIFF, typename CS>
+static hipError_t launch_apply_t(const PatchView &pv, const CS *C, const float *rs, const double *x, double *y,
+                                 hipStream_t s, int lz)
 {
     if (pv.d == 3) {
-        const size_t lds = apply3d_lds<P, STIFF, CT>();
-        hipError_t e = allow_dynamic_lds((const void *)apply3d_kernel<P, STIFF, CT>, lds);
+        const size_t lds = apply3d_lds<P, STIFF, CS>();
+        hipError_t e = allow_dynamic_lds((const void *)apply3d_kernel<P, STIFF, CS>, lds);
         if (e != hipSuccess) return e;
         int gx, gy, gz, LZ;
         apply_blocks(pv, lz, gx, gy, gz, LZ);
-        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CT>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, x, y,
-                           LZ);
+        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CS>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, rs,
+                           x, y, LZ);
     } else {
-        int64_t nel = (int64_t)pv.dir[0].K * pv.dir[1].K;
-        int64_t nb = (nel + 127) / 128;
-        if (pv.d == 2)
-            hipLaunchKernelGGL((apply_small_kernel<2, P, STIFF, CT>), dim3((unsigned)nb), dim3(128), 0, s, pv, C, x, y);
-        else
-            hipLaunchKernelGGL((apply_small_kernel<1, P, STIFF, CT>), dim3((unsigned)nb), dim3(128), 0, s, pv, C, x, y);
+        if constexpr (std::is_same<CS, __half>::value) {
+            return hipErrorInvalidValue;           // FP16 split is built for d = 3
+        } else {
+            int64_t nel = (int64_t)pv.dir[0].K * pv.dir[1].K;
+            int64_t nb = (nel + 127) / 128;
+            if (pv.d == 2)
+                hipLaunchKernelGGL((apply_small_kernel<2, P, STIFF, CS>), dim3((unsigned)nb), dim3(128), 0, s, pv, C, x,
+                                   y);
+            else
+                hipLaunchKernelGGL((apply_small_kernel<1, P, STIFF, CS>), dim3((unsigned)nb), dim3(128), 0, s, pv, C, x,
+                                   y);
+        }
     }
     return hipGetLastError();
 }
 
-template <int P, bool STIFF, typename CT>
+template <int P, bool STIFF, typename CS>
 static hipError_t launch_apply_batch_t(const TaskList &tl, int nblocks, hipStream_t s)
 {
-    const size_t lds = apply3d_lds<P, STIFF, CT>();
-    hipError_t e = allow_dynamic_lds((const void *)apply3d_persistent<P, STIFF, CT>, lds);
+    const size_t lds = apply3d_lds<P, STIFF, CS>();
+    hipError_t e = allow_dynamic_lds((const void *)apply3d_persistent<P, STIFF, CS>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((apply3d_persistent<P, STIFF, CT>), dim3(nblocks), dim3(STile<P>::NT), lds, s, tl);
+    hipLaunchKernelGGL((apply3d_persistent<P, STIFF, CS>), dim3(nblocks), dim3(STile<P>::NT), lds, s, tl);
     return hipGetLastError();
+}
+
+template <int P, bool STIFF>
+static hipError_t launch_apply_batch_o(const TaskList &tl, Prec prec, int nblocks, hipStream_t s)
+{
+    if (prec == Prec::F64) return launch_apply_batch_t<P, STIFF, double>(tl, nblocks, s);
+    if (prec == Prec::F16S) return launch_apply_batch_t<P, STIFF, __half>(tl, nblocks, s);
+    return launch_apply_batch_t<P, STIFF, float>(tl, nblocks, s);
 }
 
 template <int P>
 static hipError_t launch_apply_batch_p(const TaskList &tl, int op, Prec prec, int nblocks, hipStream_t s)
 {
-    if (prec == Prec::F64)
-        return op == 2 ? launch_apply_batch_t<P, true, double>(tl, nblocks, s)
-                       : launch_apply_batch_t<P, false, double>(tl, nblocks, s);
-    return op == 2 ? launch_apply_batch_t<P, true, float>(tl, nblocks, s)
-                   : launch_apply_batch_t<P, false, float>(tl, nblocks, s);
+    return op == 2 ? launch_apply_batch_o<P, true>(tl, prec, nblocks, s)
+                   : launch_apply_batch_o<P, false>(tl, prec, nblocks, s);
 }
 
 hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int nblocks, hipStream_t s)
@@ -737,32 +795,37 @@ hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int 
     }
 }
 
-template <int P>
-static hipError_t launch_apply_p(const PatchView &pv, int op, Prec prec, const void *C, const double *x, double *y,
-                                 hipStream_t s, int lz)
+template <int P, bool STIFF>
+static hipError_t launch_apply_o(const PatchView &pv, Prec prec, const void *C, const float *rs, const double *x,
+                                 double *y, hipStream_t s, int lz)
 {
-    if (prec == Prec::F64) {
-        if (op == 2) return launch_apply_t<P, true, double>(pv, (const double *)C, x, y, s, lz);
-        return launch_apply_t<P, false, double>(pv, (const double *)C, x, y, s, lz);
-    }
-    if (op == 2) return launch_apply_t<P, true, float>(pv, (const float *)C, x, y, s, lz);
-    return launch_apply_t<P, false, float>(pv, (const float *)C, x, y, s, lz);
+    if (prec == Prec::F64) return launch_apply_t<P, STIFF, double>(pv, (const double *)C, rs, x, y, s, lz);
+    if (prec == Prec::F16S) return launch_apply_t<P, STIFF, __half>(pv, (const __half *)C, rs, x, y, s, lz);
+    return launch_apply_t<P, STIFF, float>(pv, (const float *)C, rs, x, y, s, lz);
+}
+
+template <int P>
+static hipError_t launch_apply_p(const PatchView &pv, int op, Prec prec, const void *C, const float *rs,
+                                 const double *x, double *y, hipStream_t s, int lz)
+{
+    return op == 2 ? launch_apply_o<P, true>(pv, prec, C, rs, x, y, s, lz)
+                   : launch_apply_o<P, false>(pv, prec, C, rs, x, y, s, lz);
 }
 
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *C, const double *x, double *y,
-                        hipStream_t s, int lz)
+                        hipStream_t s, int lz, const float *rs)
 {
     hipError_t e = launch_fill(y, pv.N, 0.0, s);
     if (e != hipSuccess) return e;
     switch (pv.P) {
-    case 2: return launch_apply_p<2>(pv, op, prec, C, x, y, s, lz);
-    case 3: return launch_apply_p<3>(pv, op, prec, C, x, y, s, lz);
-    case 4: return launch_apply_p<4>(pv, op, prec, C, x, y, s, lz);
-    case 5: return launch_apply_p<5>(pv, op, prec, C, x, y, s, lz);
-    case 6: return launch_apply_p<6>(pv, op, prec, C, x, y, s, lz);
-    case 7: return launch_apply_p<7>(pv, op, prec, C, x, y, s, lz);
-    case 8: return launch_apply_p<8>(pv, op, prec, C, x, y, s, lz);
-    case 9: return launch_apply_p<9>(pv, op, prec, C, x, y, s, lz);
+    case 2: return launch_apply_p<2>(pv, op, prec, C, rs, x, y, s, lz);
+    case 3: return launch_apply_p<3>(pv, op, prec, C, rs, x, y, s, lz);
+    case 4: return launch_apply_p<4>(pv, op, prec, C, rs, x, y, s, lz);
+    case 5: return launch_apply_p<5>(pv, op, prec, C, rs, x, y, s, lz);
+    case 6: return launch_apply_p<6>(pv, op, prec, C, rs, x, y, s, lz);
+    case 7: return launch_apply_p<7>(pv, op, prec, C, rs, x, y, s, lz);
+    case 8: return launch_apply_p<8>(pv, op, prec, C, rs, x, y, s, lz);
+    case 9: return launch_apply_p<9>(pv, op, prec, C, rs, x, y, s, lz);
     default: return hipErrorInvalidValue;
     }
 }

@@ -5,6 +5,8 @@
 // coefficients (Example 1 with A = a I):
 //   mass:      w c |det J|
 //   stiffness: w a |det J| (J^-1 J^-T)_ij, i <= j   (J_ik = dG_i/dxhat_k)
+#include <hip/hip_fp16.h>
+
 #include "kernels.h"
 
 namespace sfiga {
@@ -294,6 +296,89 @@ static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream
         else
             hipLaunchKernelGGL((geom_small_kernel<1, P>), dim3((unsigned)nb), dim3(256), 0, s, pv, o);
     }
+    return hipGetLastError();
+}
+
+// FP16-split storage of a coefficient tensor (see launch_split_coef), in two
+// passes.  First the range of C / w per (element, component): one thread per
+// pair, the threads of a wavefront on consecutive elements in direction 1 so
+// that each (g3, g2) row of their points is one contiguous run.
+__global__ void split_range_kernel(PatchView pv, int nc, const float *__restrict__ c32, float *__restrict__ rs)
+{
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)d0.K * d1.K * d2.K * nc;
+    if (t >= total) return;
+    const int P = pv.P;
+    const int e1 = (int)(t % d0.K);
+    int64_t r = t / d0.K;
+    const int c = (int)(r % nc);
+    r /= nc;
+    const int e2 = (int)(r % d1.K), e3 = (int)(r / d1.K);
+    double lo = 0.0, hi = 0.0;
+    for (int g3 = 0; g3 < P; ++g3)
+        for (int g2 = 0; g2 < P; ++g2) {
+            const int q1 = e2 * P + g2, q2 = e3 * P + g3;
+            const double w23 = d1.W[q1] * d2.W[q2];
+            for (int g1 = 0; g1 < P; ++g1) {
+                const int q0 = e1 * P + g1;
+                const double v = (double)c32[coef_index(3, nc, c, q0, q1, q2, d0.Q, d1.Q)] / (d0.W[q0] * w23);
+                if (g1 == 0 && g2 == 0 && g3 == 0) lo = hi = v;
+                lo = fmin(lo, v);
+                hi = fmax(hi, v);
+            }
+        }
+    double scl = 0.5 * (hi - lo);
+    if (!(scl > 0.0)) scl = 1.0;                   // constant over the element: residual 0
+    const int64_t e = ((int64_t)e3 * d1.K + e2) * d0.K + e1;
+    rs[(e * nc + c) * 2 + 0] = (float)(0.5 * (hi + lo));
+    rs[(e * nc + c) * 2 + 1] = (float)scl;
+}
+
+// Then the residuals, the stored values in the tile-major order with the
+// threads of the grid striding over them (coalesced stores; the loads of a
+// tile row are one run of the FP32 tensor).  The grid is bounded: a 1D
+// dispatch addresses fewer than 2^32 work-items, and 118^3 elements at order 9
+// store 7.2e9 values.
+__global__ void split_store_kernel(PatchView pv, int nc, const float *__restrict__ c32, const float *__restrict__ rs,
+                                   __half *__restrict__ h16, int64_t total)
+{
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const int P = pv.P;
+    const int T = apply_tile_elems(P) * P;
+    const int gx = (d0.Q + T - 1) / T, gy = (d1.Q + T - 1) / T;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int tx = (int)(t % T);
+        int64_t r = t / T;
+        const int ty = (int)(r % T);
+        r /= T;
+        const int bx = (int)(r % gx);
+        r /= gx;
+        const int by = (int)(r % gy);
+        r /= gy;
+        const int c = (int)(r % nc), q2 = (int)(r / nc);
+        const int q0 = bx * T + tx, q1 = by * T + ty;
+        float h = 0.0f;                            // padding of the edge tiles
+        if (q0 < d0.Q && q1 < d1.Q) {
+            const int64_t e = ((int64_t)(q2 / P) * d1.K + q1 / P) * d0.K + q0 / P;
+            const double w = d0.W[q0] * d1.W[q1] * d2.W[q2];
+            const double v = (double)c32[coef_index(3, nc, c, q0, q1, q2, d0.Q, d1.Q)] / w;
+            h = (float)((v - (double)rs[(e * nc + c) * 2]) / (double)rs[(e * nc + c) * 2 + 1]);
+        }
+        h16[t] = __float2half_rn(h);
+    }
+}
+
+hipError_t launch_split_coef(const PatchView &pv, int op, const float *c32, void *h16, float *rs, hipStream_t s)
+{
+    if (pv.d != 3) return hipErrorInvalidValue;
+    const int nc = op == 2 ? 6 : 1;
+    const int64_t npair = (int64_t)pv.dir[0].K * pv.dir[1].K * pv.dir[2].K * nc;
+    hipLaunchKernelGGL(split_range_kernel, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, s, pv, nc, c32, rs);
+    const int64_t total = split_size(nc, pv.P, pv.dir[0].K, pv.dir[1].K, pv.dir[2].K);
+    const int64_t nb = (total + 255) / 256;
+    hipLaunchKernelGGL(split_store_kernel, dim3((unsigned)(nb < 65536 ? nb : 65536)), dim3(256), 0, s, pv, nc, c32,
+                       rs, static_cast<__half *>(h16), total);
     return hipGetLastError();
 }
 

@@ -10,8 +10,10 @@ namespace sfiga {
 
 // F64, F32: every contraction in that type; BF16X3: FP32 coefficients and level 1,
 // level 2 of the assembly on bf16 matrix cores with hi/lo split operands and
-// FP32 accumulation (level 3 and the values stay FP64).
-enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+// FP32 accumulation (level 3 and the values stay FP64); F16S: the apply with
+// the coefficients stored as an FP32 reference and scale per element and an
+// FP16 residual per point, contractions in FP32.
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2, F16S = 3 };
 
 // Element tile of the d = 3 tile kernels in directions 1 and 2: about 32 x 16
 // quadrature points per workgroup (one thread per quadrature column).
@@ -23,6 +25,28 @@ struct Tile {
     static constexpr int NX = E1 + P - 1, NY = E2 + P - 1;   // functions
     static constexpr int NT = TX * TY;
 };
+
+// Elements per direction of the matrix-free apply's tile in directions 1 and
+// 2 (about 16 x 16 quadrature columns per workgroup).
+__host__ __device__ constexpr int apply_tile_elems(int P) { return (16 + P - 1) / P; }
+
+// FP16-split storage of a coefficient tensor (used by the apply only), laid
+// out tile-major so that one apply workgroup reads each of its planes as one
+// contiguous block: [q3][comp][tile_y][tile_x][ty][tx], tiles of
+// T = apply_tile_elems(P) * P points per direction (edge tiles padded).
+__host__ __device__ inline int64_t split_index(int ncomp, int comp, int q0, int q1, int q2, int P, int K0, int K1)
+{
+    const int T = apply_tile_elems(P) * P;
+    const int gx = (K0 * P + T - 1) / T, gy = (K1 * P + T - 1) / T;
+    const int bx = q0 / T, by = q1 / T;
+    return ((((int64_t)q2 * ncomp + comp) * gy + by) * gx + bx) * T * T + (q1 - by * T) * T + (q0 - bx * T);
+}
+__host__ __device__ inline int64_t split_size(int ncomp, int P, int K0, int K1, int K2)
+{
+    const int T = apply_tile_elems(P) * P;
+    const int64_t gx = (K0 * P + T - 1) / T, gy = (K1 * P + T - 1) / T;
+    return (int64_t)K2 * P * ncomp * gy * gx * T * T;
+}
 
 struct PatchView {
     int d, P;
@@ -59,6 +83,7 @@ __host__ __device__ inline int64_t coef_index(int d, int ncomp, int comp, int q0
 struct BatchTask {
     PatchView pv;
     const void *C;         // coefficient tensor of the operator at the precision
+    const float *rs;       // per-element reference and scale (FP16-split storage)
     void *ws;              // level-2 workspace of the assembly
     double *out;           // assembly values or y, offset to the patch
     const double *x;       // apply input, offset to the patch
@@ -114,8 +139,15 @@ hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_in
 hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
 // op: 1 mass, 2 stiffness; c: coefficient tensor of that op at prec
 // lz: element layers per workgroup in direction 3 (0 = default)
+// rs: per-element reference and scale of the F16S storage (null otherwise)
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, const double *x, double *y,
-                        hipStream_t s, int lz = 0);
+                        hipStream_t s, int lz = 0, const float *rs = nullptr);
+// F16S storage from the FP32 coefficient tensor c32 of op (d = 3): per element
+// and component the reference r = (max + min) / 2 and scale s = (max - min) / 2
+// of C / w over the element's points (rs [K3][K2][K1][ncomp][2]), and per point
+// h = (C / w - r) / s rounded to FP16 (h16, split_index layout, split_size
+// values; padding 0), w the product of the point's Gauss weights.
+hipError_t launch_split_coef(const PatchView &pv, int op, const float *c32, void *h16, float *rs, hipStream_t s);
 // ws: device workspace of ws_bytes for the d = 3 level-2 partials (see
 // assemble_workspace_bytes; unused for d <= 2)
 // t1 (rows m1 per level-1/2 tile) and seg (rows m3 per level-3 segment)

@@ -38,15 +38,17 @@ struct sf_patch {
     double *dctrl = nullptr;
     int *dflag = nullptr;
     Coef coef[2];                 // [0] mass, [1] stiffness
-    void *C[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [op][FP64, FP32 storage]
-    bool ready[2][3] = {{false, false, false}, {false, false, false}};   // [op][precision mode]
+    // [op][storage: FP64, FP32, FP16 residual of the FP16 split]
+    void *C[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    float *rs[2] = {nullptr, nullptr};   // [op] per-element reference and scale of the FP16 split
+    bool ready[2][4] = {};               // [op][precision mode]
     // level-2 workspace of the d = 3 assembly, sized once for the largest
     // (operator, precision) so that captured graphs never see it move
     void *ws = nullptr;
     size_t ws_bytes = 0;
     // autotuned assembly tile parameters per [op][prec] (-1: not yet tuned)
-    int tune_t1[2][3] = {{-1, -1, -1}, {-1, -1, -1}}, tune_seg[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
-    int tune_lz[2][3] = {{-1, -1, -1}, {-1, -1, -1}};   // apply: layers per workgroup
+    int tune_t1[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}}, tune_seg[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    int tune_lz[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};   // apply: layers per workgroup
     PatchView view{};
 };
 
@@ -118,18 +120,22 @@ hipError_t upload(T **dst, const T *src, size_t n, hipStream_t s)
 }
 
 // Precision modes: 0 FP64, 1 FP32, 2 BF16 split (FP32 coefficients and
-// level 1, level 2 of the assembly on bf16 matrix cores with a hi/lo split).
+// level 1, level 2 of the assembly on bf16 matrix cores with a hi/lo split;
+// assembly only), 3 FP16 split (FP16 residuals of the coefficients with a
+// per-element FP32 reference and scale; apply only).
 bool prec_index(sf_precision prec, int &pi)
 {
     if (prec == SF_FP64) { pi = 0; return true; }
     if (prec == SF_FP32) { pi = 1; return true; }
     if (prec == SF_BF16_SPLIT) { pi = 2; return true; }
+    if (prec == SF_FP16_SPLIT) { pi = 3; return true; }
     return false;
 }
 
-int cidx(int pi) { return pi == 0 ? 0 : 1; }                      // coefficient tensor storage
+int cidx(int pi) { return pi == 0 ? 0 : (pi == 3 ? 2 : 1); }       // coefficient tensor storage
+int geom_storage(int pi) { return pi == 0 ? 0 : 1; }                // storage the geometry kernel writes
 Prec asm_prec(int pi) { return pi == 0 ? Prec::F64 : (pi == 1 ? Prec::F32 : Prec::BF16X3); }
-Prec apply_prec(int pi) { return pi == 0 ? Prec::F64 : Prec::F32; }   // no dense contraction for bf16
+Prec apply_prec(int pi) { return pi == 0 ? Prec::F64 : (pi == 3 ? Prec::F16S : Prec::F32); }
 
 int ncomp(int op_idx, int d) { return op_idx == 0 ? 1 : d * (d + 1) / 2; }
 
@@ -147,6 +153,7 @@ void free_patch_memory(sf_patch *p)
     (void)hipFree(p->ws);
     for (auto &a : p->C)
         for (void *c : a) (void)hipFree(c);
+    for (float *r : p->rs) (void)hipFree(r);
 }
 
 }  // namespace
@@ -324,7 +331,7 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
     }
     int oi = op == SF_MASS ? 0 : 1;
     p->coef[oi] = c;
-    p->ready[oi][0] = p->ready[oi][1] = p->ready[oi][2] = false;
+    for (bool &r : p->ready[oi]) r = false;
     return SF_OK;
 }
 
@@ -352,36 +359,48 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     ctx->err.clear();
     if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
     int pi;
-    if (!prec_index(prec, pi)) {
-        if (prec == SF_FP16_SPLIT)
-            return fail(ctx, SF_EUNSUPPORTED, "FP16 split not built: the level-2 operands fall below the FP16 range");
-        return fail(ctx, SF_EINVAL, "bad precision");
-    }
+    if (!prec_index(prec, pi)) return fail(ctx, SF_EINVAL, "bad precision");
+    if (pi == 3 && p->d != 3) return fail(ctx, SF_EUNSUPPORTED, "the FP16-split storage is built for d = 3");
     hipStream_t s = ctx->stream;
-    const int ci = cidx(pi);
-    const size_t esz = ci == 0 ? sizeof(double) : sizeof(float);
+    const int gi = geom_storage(pi);
+    const size_t esz = gi == 0 ? sizeof(double) : sizeof(float);
+    const int64_t nel = (int64_t)p->view.dir[0].K * p->view.dir[1].K * p->view.dir[2].K;
     GeomOut o{};
-    o.prec = ci == 0 ? Prec::F64 : Prec::F32;
+    o.prec = gi == 0 ? Prec::F64 : Prec::F32;
     o.bad_det = p->dflag;
     o.coef_mass = p->coef[0];
     o.coef_stiff = p->coef[1];
+    auto alloc = [&](void **ptr, size_t bytes) -> sf_status {
+        if (*ptr) return SF_OK;
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) {
+            *ptr = nullptr;
+            return hip_fail(ctx, e, "coefficient tensor allocation");
+        }
+        return SF_OK;
+    };
     for (int oi = 0; oi < 2; ++oi) {
         unsigned bit = oi == 0 ? SF_MASS : SF_STIFF;
         if (!(ops & bit)) continue;
         if (p->coef[oi].kind == 2 && !p->coef[oi].qp) return fail(ctx, SF_EINVAL, "missing quadrature values");
-        if (!p->C[oi][ci]) {
-            hipError_t e = hipMalloc(&p->C[oi][ci], esz * (size_t)p->view.Q * ncomp(oi, p->d));
-            if (e != hipSuccess) {
-                p->C[oi][ci] = nullptr;
-                return hip_fail(ctx, e, "coefficient tensor allocation");
-            }
-        }
-        for (int m = 0; m < 3; ++m)
-            if (cidx(m) == ci) p->ready[oi][m] = false;
-        if (oi == 0) o.c_mass = p->C[oi][ci]; else o.c_stiff = p->C[oi][ci];
+        const size_t nq = (size_t)p->view.Q * ncomp(oi, p->d);
+        sf_status st = alloc(&p->C[oi][gi], esz * nq);
+        if (st == SF_OK && pi == 3)
+            st = alloc(&p->C[oi][2], 2 * (size_t)split_size(ncomp(oi, p->d), p->P, p->view.dir[0].K,
+                                                              p->view.dir[1].K, p->view.dir[2].K));
+        if (st == SF_OK && pi == 3) st = alloc((void **)&p->rs[oi], sizeof(float) * 2 * ncomp(oi, p->d) * nel);
+        if (st != SF_OK) return st;
+        // the modes stored in what this call rewrites are stale until it is done
+        for (int m = 0; m < 4; ++m)
+            if (geom_storage(m) == gi) p->ready[oi][m] = false;
+        if (oi == 0) o.c_mass = p->C[oi][gi]; else o.c_stiff = p->C[oi][gi];
     }
     hipError_t e = sync ? hipMemsetAsync(p->dflag, 0, sizeof(int), s) : hipSuccess;
     if (e == hipSuccess) e = launch_geometry(p->view, o, s);
+    if (pi == 3)
+        for (int oi = 0; oi < 2 && e == hipSuccess; ++oi)
+            if (ops & (oi == 0 ? SF_MASS : SF_STIFF))
+                e = launch_split_coef(p->view, oi + 1, (const float *)p->C[oi][1], p->C[oi][2], p->rs[oi], s);
     int flag = 0;
     if (sync) {
         if (e == hipSuccess) e = hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -390,9 +409,12 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     if (e != hipSuccess) return hip_fail(ctx, e, "geometry step");
     if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
     for (int oi = 0; oi < 2; ++oi)
-        if (ops & (oi == 0 ? SF_MASS : SF_STIFF))
+        if (ops & (oi == 0 ? SF_MASS : SF_STIFF)) {
+            // FP32 storage serves FP32 and BF16 split; the FP16 split needs its own pass
             for (int m = 0; m < 3; ++m)
-                if (cidx(m) == ci) p->ready[oi][m] = true;     // FP32 storage serves FP32 and BF16 split
+                if (geom_storage(m) == gi) p->ready[oi][m] = true;
+            if (pi == 3) p->ready[oi][3] = true;
+        }
     return SF_OK;
 }
 
@@ -430,15 +452,19 @@ sf_status sf_csr_pattern(sf_patch *p, int64_t *row_ptr, int32_t *col_ind)
     return SF_OK;
 }
 
-static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &pi)
+// for_apply: the matrix-free apply (the FP16 split is its mode; the BF16 split
+// is a mode of the assembly only)
+static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &pi, bool for_apply)
 {
     sf_ctx *ctx = p->ctx;
     if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
-    if (!prec_index(prec, pi)) {
-        if (prec == SF_FP16_SPLIT)
-            return fail(ctx, SF_EUNSUPPORTED, "FP16 split not built: the level-2 operands fall below the FP16 range");
-        return fail(ctx, SF_EINVAL, "bad precision");
-    }
+    if (!prec_index(prec, pi)) return fail(ctx, SF_EINVAL, "bad precision");
+    if (for_apply && pi == 2)
+        return fail(ctx, SF_EUNSUPPORTED, "BF16 split is a mode of the assembly; the reduced-storage apply is "
+                                          "SF_FP16_SPLIT");
+    if (!for_apply && pi == 3)
+        return fail(ctx, SF_EUNSUPPORTED, "FP16 split is a storage of the matrix-free apply; assemble at FP64, FP32 "
+                                          "or BF16 split");
     for (int oi = 0; oi < 2; ++oi)
         if ((ops & (oi == 0 ? SF_MASS : SF_STIFF)) && !p->ready[oi][pi])
             return fail(ctx, SF_EINVAL, "operator not prepared at this precision (call sf_patch_prepare)");
@@ -536,7 +562,7 @@ sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, 
     if (!p) return SF_EINVAL;
     p->ctx->err.clear();
     int pi;
-    sf_status st = check_ready(p, ops, prec, pi);
+    sf_status st = check_ready(p, ops, prec, pi, false);
     if (st != SF_OK) return st;
     if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(p->ctx, SF_EINVAL, "null output");
     st = ensure_workspace(p);
@@ -555,7 +581,7 @@ sf_status sf_assemble_noalloc(sf_patch *p, unsigned ops, sf_precision prec, doub
     sf_ctx *ctx = p->ctx;
     ctx->err.clear();
     int pi;
-    sf_status st = check_ready(p, ops, prec, pi);
+    sf_status st = check_ready(p, ops, prec, pi, false);
     if (st != SF_OK) return st;
     if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(ctx, SF_EINVAL, "null output");
     if (p->d == 3) {
@@ -589,7 +615,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
     p->ctx->err.clear();
     if (op != SF_MASS && op != SF_STIFF) return fail(p->ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
     int pi;
-    sf_status st = check_ready(p, op, prec, pi);
+    sf_status st = check_ready(p, op, prec, pi, true);
     if (st != SF_OK) return st;
     if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
     if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
@@ -605,7 +631,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             hipEvent_t e0 = nullptr, e1 = nullptr;
             hipError_t e = hipEventCreate(&e0);
             if (e == hipSuccess) e = hipEventCreate(&e1);
-            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s);   // warm-up
+            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, 0, p->rs[oi]);   // warm-up
             float best = 1e30f;
             for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
                 if (e != hipSuccess || lz > p->view.dir[2].K) break;
@@ -613,7 +639,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
                     float t = 0.f;
                     e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz);
+                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz, p->rs[oi]);
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -629,7 +655,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
         }
     }
-    hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi]);
+    hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi], p->rs[oi]);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
     return SF_OK;
 }
@@ -718,6 +744,7 @@ static HostTasks build_tasks(const sf_batch *b, int kernel, int P, int oi, int p
         BatchTask T{};
         T.pv = p->view;
         T.C = p->C[oi][cidx(pi)];
+        T.rs = p->rs[oi];
         T.ws = p->ws;
         const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
         T.gy = T.gz = 1;
@@ -927,7 +954,8 @@ static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const 
                 double *dst = io_in.vals[oi] + z0;
                 e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, p->ws, p->ws_bytes, s);
             } else {
-                e = launch_apply(p->view, oi + 1, apply_prec(pi), p->C[oi][cidx(pi)], io_in.x + r0, io_in.y + r0, s);
+                e = launch_apply(p->view, oi + 1, apply_prec(pi), p->C[oi][cidx(pi)], io_in.x + r0, io_in.y + r0, s, 0,
+                                 p->rs[oi]);
             }
             if (e != hipSuccess) return hip_fail(b->ctx, e, "per-patch kernel");
         }
@@ -978,7 +1006,7 @@ sf_status sf_batch_assemble(sf_batch *b, unsigned ops, sf_precision prec, int64_
     if (((ops & SF_MASS) && !vm) || ((ops & SF_STIFF) && !vs)) return fail(b->ctx, SF_EINVAL, "null output");
     int pi = 0;
     for (sf_patch *p : b->patches) {
-        sf_status st = check_ready(p, ops, prec, pi);
+        sf_status st = check_ready(p, ops, prec, pi, false);
         if (st != SF_OK) return st;
         st = ensure_workspace(p);
         if (st != SF_OK) return st;
@@ -999,7 +1027,7 @@ sf_status sf_batch_apply(sf_batch *b, unsigned op, sf_precision prec, const doub
     if (!x || !y || x == y) return fail(b->ctx, SF_EINVAL, "bad vectors");
     int pi = 0;
     for (sf_patch *p : b->patches) {
-        sf_status st = check_ready(p, op, prec, pi);
+        sf_status st = check_ready(p, op, prec, pi, true);
         if (st != SF_OK) return st;
     }
     BatchIO io;

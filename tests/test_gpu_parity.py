@@ -25,9 +25,19 @@ TOL32 = 1e-6
 # term carries about 2^-16 (1.5e-5) relative error before the FP32 and FP64
 # sums, which average it down; measured at most 4.2e-6 (orders 2-9)
 TOLBF = 2e-5
+# FP16 split (matrix-free apply): per element and component C / w = r + s h
+# with h in [-1, 1] rounded to FP16, so each coefficient is within
+# 2^-12 s w of the FP32 one; s is the half range of C / w over the element
+# (the variation of the geometry and the coefficient within it), well below
+# max |C / w|.  Measured at most 1.6e-5 over orders 2-9 (err_y).
+TOL16 = 1e-4
 
 
-def _full_parity(knots, p, ctrl, coef, ops=(sf.SF_MASS, sf.SF_STIFF), prec=sf.SF_FP64, tol=TOL64, seed=0):
+def _full_parity(knots, p, ctrl, coef, ops=(sf.SF_MASS, sf.SF_STIFF), prec=sf.SF_FP64, tol=TOL64, seed=0,
+                 assemble=True, apply=True):
+    """Pattern, values and y = A x of the operators against the oracle's full
+    assembly (and SpMV) on the same inputs; assemble / apply select what the
+    precision mode supports."""
     P = oracle.Problem(knots, p, ctrl, coef)
     x = inputs.random_vector(P.N, seed)
     rp_o, ci_o = P.pattern()
@@ -39,21 +49,24 @@ def _full_parity(knots, p, ctrl, coef, ops=(sf.SF_MASS, sf.SF_STIFF), prec=sf.SF
         out = {}
         for op in ops:
             _, _, v_o = P.assemble(op, pattern=(rp_o, ci_o))
-            v = g.assemble(op, prec)
-            assert not np.isnan(v).any()
-            eA = err_A(v, v_o)
-            A = oracle.csr_to_dense(rp_o, ci_o, v_o, P.N) if P.N <= 4000 else None
-            y_o = P.apply(op, x)
-            y = g.apply(op, x, prec)
-            absAx = np.abs(A) @ np.abs(x) if A is not None else None
-            if absAx is None:
-                absAx = np.zeros(P.N)
-                np.add.at(absAx, np.repeat(np.arange(P.N), np.diff(rp_o)), np.abs(v_o) * np.abs(x[ci_o]))
-            ey = err_y(y, y_o, absAx)
-            record("err_A", prec, eA)
-            record("err_y", prec, ey)
-            assert eA <= tol, (op, eA)
-            assert ey <= tol, (op, ey)
+            eA = ey = 0.0
+            if assemble:
+                v = g.assemble(op, prec)
+                assert not np.isnan(v).any()
+                eA = err_A(v, v_o)
+                record("err_A", prec, eA)
+                assert eA <= tol, (op, eA)
+            if apply:
+                A = oracle.csr_to_dense(rp_o, ci_o, v_o, P.N) if P.N <= 4000 else None
+                y_o = P.apply(op, x)
+                y = g.apply(op, x, prec)
+                absAx = np.abs(A) @ np.abs(x) if A is not None else None
+                if absAx is None:
+                    absAx = np.zeros(P.N)
+                    np.add.at(absAx, np.repeat(np.arange(P.N), np.diff(rp_o)), np.abs(v_o) * np.abs(x[ci_o]))
+                ey = err_y(y, y_o, absAx)
+                record("err_y", prec, ey)
+                assert ey <= tol, (op, ey)
             out[op] = (eA, ey)
         return out
 
@@ -115,11 +128,25 @@ def test_3d_bf16_split_mode(K, p):
     """Level 2 of the assembly on bf16 matrix cores with hi/lo split operands
     and FP32 accumulation (FP32 coefficients and level 1, FP64 level 3 and
     values); the apply runs its FP32 path.  Parity unpinned by the paper:
-    checked against the FP64 oracle with the bound TOLBF."""
+    checked against the FP64 oracle with the bound TOLBF.  BF16 split is a
+    mode of the assembly: the apply refuses it."""
     kn, ctrl = inputs.perturbed_geometry(K, p, seed=4)
-    res = _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_BF16_SPLIT, tol=TOLBF)
+    res = _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_BF16_SPLIT, tol=TOLBF, apply=False)
     # the split keeps far more than bf16 alone (2^-9 ~ 2e-3) would
     assert max(eA for eA, _ in res.values()) < 1e-4
+
+
+@pytest.mark.parametrize("K,p", [((7, 3, 5), 2), ((13, 4, 6), 3), ((21, 3, 5), 4), ((3, 4, 3), 5), ((4, 3, 2), 6),
+                                 ((2, 3, 2), 7), ((2, 2, 2), 8), ((1, 1, 2), 9)])
+def test_3d_fp16_split_apply(K, p):
+    """Matrix-free apply with the coefficients stored as FP16 residuals of a
+    per-element FP32 reference and scale (2 bytes per component), several
+    tiles and ragged edges, mass and stiffness, against the FP64 oracle with
+    the bound TOL16; the assembly refuses the mode."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=14)
+    res = _full_parity(kn, p, ctrl, ("sinprod", 0.5), prec=sf.SF_FP16_SPLIT, tol=TOL16, assemble=False)
+    # far more than FP16 alone would keep (2^-11 ~ 5e-4 of the values)
+    assert max(ey for _, ey in res.values()) < 5e-5
 
 
 @pytest.mark.parametrize("K,p", [((2, 3, 2), 7), ((2, 2, 2), 8), ((1, 1, 2), 9)])
@@ -335,6 +362,19 @@ def test_3d_128cubed_p6_sampled_rows(prec, tol):
         assert np.abs(y1).max() <= (1e-12 if prec == sf.SF_FP64 else 1e-5) * vmax
 
 
+def test_3d_128cubed_p6_fp16_split_apply():
+    """The 128^3 order-6 patch: matrix-free apply with the FP16-split
+    coefficient storage, on the sampled rows of the large-patch reference."""
+    L = _large_reference()
+    w = L["w"]
+    with GpuPatch(w["knots"], w["p"], w["ctrl"], w["coef"]) as g:
+        g.prepare(sf.SF_STIFF, sf.SF_FP16_SPLIT)
+        y = g.apply(sf.SF_STIFF, w["x"], sf.SF_FP16_SPLIT)
+        ey = float(np.abs(y[L["rows"]] - L["y"]).max() / L["scale"])
+        record("err_y", sf.SF_FP16_SPLIT, ey)
+        assert ey <= TOL16, ey
+
+
 @pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8, 9])
 def test_order_sweep_apply_sampled(p):
     """d = 3, K = 127 - p per direction (N = 126^3 for every order), matrix-free
@@ -347,6 +387,9 @@ def test_order_sweep_apply_sampled(p):
     _sampled_parity(w, (sf.SF_STIFF,), nrandom=4 if coarse else 16, assemble=False, coarse=coarse, band=band)
     if p in (2, 4, 6, 8):
         _sampled_parity(w, (sf.SF_STIFF,), prec=sf.SF_FP32, tol=TOL32, nrandom=4, assemble=False, coarse=True,
+                        band="cross")
+    if p in (3, 5, 7, 9):
+        _sampled_parity(w, (sf.SF_STIFF,), prec=sf.SF_FP16_SPLIT, tol=TOL16, nrandom=4, assemble=False, coarse=True,
                         band="cross")
 
 
@@ -557,6 +600,46 @@ def test_batched_mixed_precision(prec, tol):
                 g.close()
 
 
+def test_batched_fp16_split_apply():
+    """Batched matrix-free apply with the FP16-split coefficient storage
+    (persistent kernels, captured graph on a side stream, replayed), patch by
+    patch against the oracle's product."""
+    import torch
+    from tests.gpu_util import side_ctx
+    c, stream = side_ctx()
+    Ks, ps = inputs.batched_draw(12, seed=6, kmin=2, kmax=7, pmin=2, pmax=6)
+    with torch.cuda.stream(stream):
+        patches, refs, xs = [], [], []
+        for b in range(12):
+            kn, ctrl, x = inputs.batched_patch(b, Ks[b], ps[b])
+            g = GpuPatch(kn, int(ps[b]), ctrl, context=c)
+            g.prepare(sf.SF_STIFF, sf.SF_FP16_SPLIT)
+            patches.append(g)
+            P = oracle.Problem(kn, int(ps[b]), ctrl)
+            rp_o, ci_o, v_o = P.assemble(sf.SF_STIFF)
+            A = oracle.csr_to_dense(rp_o, ci_o, v_o, P.N)
+            refs.append((A @ x, np.abs(A) @ np.abs(x)))
+            xs.append(x)
+        try:
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            ro, _ = sf.sf_batch_offsets(c, bt, 12)
+            xall = torch.as_tensor(np.concatenate(xs)).cuda()
+            y = torch.empty(int(ro[-1]), dtype=torch.float64, device="cuda")
+            for rep in range(3):
+                y.fill_(float("nan"))
+                sf.sf_batch_apply(c, bt, sf.SF_STIFF, sf.SF_FP16_SPLIT, xall, y)
+                stream.synchronize()
+                yn = y.cpu().numpy()
+                for b in range(12):
+                    ey = err_y(yn[ro[b]:ro[b + 1]], *refs[b])
+                    record("err_y", sf.SF_FP16_SPLIT, ey)
+                    assert ey <= TOL16, (rep, b, ey)
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
+
+
 def test_batched_equals_single_patch():
     """Tile shapes (tuned separately for the single-patch and the batched
     launches) do not change the summation order of any entry: the batched
@@ -651,8 +734,13 @@ def test_error_paths():
         with pytest.raises(sf.SfError) as e:
             g.prepare(prec=sf.SF_BF16_SPLIT + 7)
         assert e.value.status == sf.SF_EINVAL
+        g.prepare(sf.SF_STIFF, sf.SF_FP16_SPLIT)
         with pytest.raises(sf.SfError) as e:
-            g.prepare(prec=sf.SF_FP16_SPLIT)
+            g.assemble(sf.SF_STIFF, sf.SF_FP16_SPLIT)     # a storage of the apply only
+        assert e.value.status == sf.SF_EUNSUPPORTED
+        g.prepare(sf.SF_STIFF, sf.SF_BF16_SPLIT)
+        with pytest.raises(sf.SfError) as e:
+            g.apply(sf.SF_STIFF, np.ones(g.N), sf.SF_BF16_SPLIT)   # a mode of the assembly only
         assert e.value.status == sf.SF_EUNSUPPORTED
         g.prepare()
         assert g.assemble(sf.SF_STIFF).shape == (g.nnz,)     # still usable after errors
