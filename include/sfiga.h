@@ -169,6 +169,19 @@ sf_status sf_patch_set_coef(sf_patch *patch, unsigned op, sf_coef_kind kind, con
  * users).  Asynchronous. */
 sf_status sf_patch_quad_points(sf_patch *patch, double *dev_xyz);
 
+/* Evaluation of a discrete function u = sum_n u_n phi_n at every quadrature
+ * point by sum factorization (Sec. 6.2, Algorithm 3: the contractions run
+ * direction by direction over the tensor grid of points, cost p^{d+1} per
+ * point instead of p^{2d}), with its physical gradient J^-T grad_hat u, where
+ * the Jacobian of the geometry map is evaluated in the same pass.  dev_u
+ * (device, [N] FP64, lexicographic) holds the coefficients u_n; dev_val
+ * (device, [Q]) receives u and dev_grad (device, [Q][d]) the gradient, both
+ * lexicographic with quadrature direction 1 fastest (the point order of
+ * sf_patch_quad_points); either output may be NULL, not both.  Independent of
+ * sf_patch_prepare (no coefficient tensor is touched, no det J record).
+ * Asynchronous. */
+sf_status sf_patch_eval(sf_patch *patch, const double *dev_u, double *dev_val, double *dev_grad);
+
 /* Geometry step (Sec. 6.3): evaluates G and its Jacobian at all quadrature
  * points by sum factorization (Algorithm 3), and folds weight, coefficient,
  * |det J| and J^-1 J^-T into the quadrature-coefficient tensor of each

@@ -74,9 +74,10 @@ def _lib():
     lib.orc_apply.argtypes = prob + [ctypes.c_int, f64p, f64p, ctypes.c_int]
     lib.orc_apply_elements.argtypes = prob + [ctypes.c_int, f64p, ctypes.c_int64, i64p, f64p,
                                               ctypes.c_int]
+    lib.orc_eval.argtypes = prob + [f64p, f64p, f64p, f64p, ctypes.c_int]
     lib.orc_measure.argtypes = prob + [f64p]
     for f in (lib.orc_pattern, lib.orc_assemble, lib.orc_rows, lib.orc_apply_rows,
-              lib.orc_apply, lib.orc_apply_elements, lib.orc_measure):
+              lib.orc_apply, lib.orc_apply_elements, lib.orc_eval, lib.orc_measure):
         f.restype = ctypes.c_int
     lib.orc_set_defect.argtypes = [ctypes.c_int]
     lib.orc_set_defect.restype = None
@@ -350,6 +351,23 @@ class Problem:
                                               len(els), els.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                               y.ctypes.data_as(f64), threads))
         return y[np.asarray(rows, dtype=np.int64)]
+
+    def nquad(self):
+        return int(np.prod([ne * p for ne, p in zip(self.nel, self.orders)]))
+
+    def eval(self, u, threads=0):
+        """Values [Q], physical gradients [Q, d] and physical points [Q, d] of
+        u = sum u_n phi_n at the quadrature points (lexicographic, direction 1
+        fastest), by plain sums over each point's active functions."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        Q = self.nquad()
+        val = np.zeros(Q)
+        grad = np.zeros((Q, self.d))
+        xyz = np.zeros((Q, self.d))
+        f64 = ctypes.POINTER(ctypes.c_double)
+        self._check(_lib().orc_eval(*self._args(), u.ctypes.data_as(f64), val.ctypes.data_as(f64),
+                                    grad.ctypes.data_as(f64), xyz.ctypes.data_as(f64), threads))
+        return val, grad, xyz
 
     def measure(self):
         out = ctypes.c_double(0.0)

@@ -153,6 +153,7 @@ typedef struct {
     double grad[MAXLOC][MAXD];  /* J^-T grad_hat phi_n(x): physical gradient */
     double wdet;                /* w(x) |det J(x)| */
     double coef;                /* coefficient at G(x) */
+    double xphys[MAXD];         /* G(x), the physical point */
 } qp_t;
 
 static int eval_qp(const prob_t *P, const int *e, const int *g, qp_t *Q)
@@ -232,6 +233,7 @@ static int eval_qp(const prob_t *P, const int *e, const int *g, qp_t *Q)
         inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
         inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
     }
+    for (int i = 0; i < d; ++i) Q->xphys[i] = G[i];
     Q->wdet = orc_defect == 3 ? wq : wq * fabs(det);
     if (orc_defect == 5) {
         /* element centre of a uniform reference mesh, not G(xhat) */
@@ -664,6 +666,69 @@ int orc_apply_elements(PROB_ARGS, int op, const double *x, int64_t nlist, const 
             }
             free(Q);
         }
+    }
+    prob_free(&P);
+    return err;
+}
+
+/* Values and physical gradients of u = sum_n u_n phi_n at every quadrature
+ * point (the quantities Algorithm 3 produces, Sec. 6.2), by the plain sums
+ * over the p^d active functions of the point's element: u(x) = sum u_n phi_n,
+ * grad u = sum u_n J^-T grad_hat phi_n.  Points in lexicographic order,
+ * quadrature direction 1 fastest; val [Q], grad [Q][d], xyz [Q][d] (the
+ * physical points G(x)); any output may be NULL. */
+int orc_eval(PROB_ARGS, const double *u, double *val, double *grad, double *xyz, int nthreads)
+{
+    prob_t P;
+    int st = prob_init(&P, PROB_PASS);
+    if (st) return st;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t nel_total = 1;
+    int nq[MAXD] = {1, 1, 1};
+    for (int k = 0; k < P.d; ++k) {
+        nel_total *= P.nel[k];
+        nq[k] = P.nel[k] * P.p[k];
+    }
+    int err = ORC_OK;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t el = 0; el < nel_total; ++el) {
+        int e[MAXD] = {0, 0, 0};
+        int64_t r = el;
+        for (int k = 0; k < P.d; ++k) {
+            e[k] = (int)(r % P.nel[k]);
+            r /= P.nel[k];
+        }
+        qp_t *Q = malloc(sizeof(qp_t));
+        int nqp = 1;
+        for (int k = 0; k < P.d; ++k) nqp *= P.p[k];
+        for (int q = 0; q < nqp; ++q) {
+            int g[MAXD] = {0, 0, 0};
+            int rr = q;
+            for (int k = 0; k < P.d; ++k) { g[k] = rr % P.p[k]; rr /= P.p[k]; }
+            if (eval_qp(&P, e, g, Q) != ORC_OK) {
+                #pragma omp atomic write
+                err = ORC_EGEOM;
+                break;
+            }
+            int64_t qlin = 0, stride = 1;
+            for (int k = 0; k < P.d; ++k) {
+                qlin += (int64_t)(e[k] * P.p[k] + g[k]) * stride;
+                stride *= nq[k];
+            }
+            double v = 0.0, gu[MAXD] = {0, 0, 0};
+            for (int b = 0; b < Q->nloc; ++b) {
+                v += u[Q->gidx[b]] * Q->val[b];
+                for (int k = 0; k < P.d; ++k) gu[k] += u[Q->gidx[b]] * Q->grad[b][k];
+            }
+            if (val) val[qlin] = v;
+            for (int k = 0; k < P.d; ++k) {
+                if (grad) grad[qlin * P.d + k] = gu[k];
+                if (xyz) xyz[qlin * P.d + k] = Q->xphys[k];
+            }
+        }
+        free(Q);
     }
     prob_free(&P);
     return err;

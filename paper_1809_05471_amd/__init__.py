@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4:
 
 EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target", "sf_host_tables_1d",
             "sf_patch_create",
-            "sf_patch_info", "sf_patch_set_coef", "sf_patch_quad_points", "sf_patch_prepare",
+            "sf_patch_info", "sf_patch_set_coef", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
             "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_assemble_noalloc", "sf_apply", "sf_patch_destroy", "sf_batch_create",
             "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_batch_destroy"]
 
@@ -62,6 +62,7 @@ def lib():
         "sf_patch_info": (st, [vp, i64p, i64p, i64p]),
         "sf_patch_set_coef": (st, [vp, ctypes.c_uint, ctypes.c_int, vp]),
         "sf_patch_quad_points": (st, [vp, vp]),
+        "sf_patch_eval": (st, [vp, vp, vp, vp]),
         "sf_patch_prepare": (st, [vp, ctypes.c_uint, ctypes.c_int]),
         "sf_patch_prepare_async": (st, [vp, ctypes.c_uint, ctypes.c_int]),
         "sf_patch_geometry_check": (st, [vp]),
@@ -185,6 +186,10 @@ def sf_patch_set_coef(ctx, patch, op, kind, value=None, qp_values=None):
 
 def sf_patch_quad_points(ctx, patch, xyz):
     _check(lib().sf_patch_quad_points(patch, _ptr(xyz)), ctx)
+
+
+def sf_patch_eval(ctx, patch, u, val=None, grad=None):
+    _check(lib().sf_patch_eval(patch, _ptr(u), _ptr(val), _ptr(grad)), ctx)
 
 
 def sf_patch_prepare(ctx, patch, ops, prec=SF_FP64):

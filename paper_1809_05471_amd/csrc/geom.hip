@@ -19,7 +19,7 @@ __device__ __forceinline__ void store_coef(void *base, int64_t idx, double v)
 
 __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3][3], double w, int64_t qlin,
                                              int q0, int q1, int q2, const PatchView &pv, const GeomOut &o,
-                                             bool f32)
+                                             bool f32, const double *uh)
 {
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
@@ -39,6 +39,12 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
     inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
     const double wd = w * fabs(det);
     const int Q0 = pv.dir[0].Q, Q1 = pv.dir[1].Q;
+    if (uh) {
+        // u and its physical gradient J^-T grad_hat u: (J^-T g)_i = sum_k (J^-1)_ki g_k
+        if (o.uval) o.uval[qlin] = uh[0];
+        if (o.ugrad)
+            for (int i = 0; i < 3; ++i) o.ugrad[qlin * 3 + i] = inv[0][i] * uh[1] + inv[1][i] * uh[2] + inv[2][i] * uh[3];
+    }
     if (o.xyz) {
         o.xyz[qlin * 3 + 0] = G[0];
         o.xyz[qlin * 3 + 1] = G[1];
@@ -67,27 +73,32 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
 // needs three barriers; one plane at a time above, to bound LDS).
 template <int P> struct GeomPlanes { static constexpr int NPS = P <= 4 ? P : 1; };
 
-template <int P>
+// EVAL: a fourth field, the coefficients u_n of a discrete function, goes
+// through the same contractions (Algorithm 3 evaluates u = sum u_n phi_n and
+// its reference derivatives on the grid of quadrature points).
+template <int P, bool EVAL>
 constexpr size_t geom3d_lds()
 {
     using TL = Tile<P>;
     constexpr int NPS = GeomPlanes<P>::NPS;
-    return sizeof(double) * (3 * P * TL::NY * TL::NX + 6 * NPS * TL::NY * TL::NX + 9 * NPS * TL::TY * TL::NX +
-                             2 * (TL::E1 + TL::E2) * P * P);
+    constexpr int NFL = EVAL ? 4 : 3;
+    return sizeof(double) * (NFL * P * TL::NY * TL::NX + 2 * NFL * NPS * TL::NY * TL::NX +
+                             3 * NFL * NPS * TL::TY * TL::NX + 2 * (TL::E1 + TL::E2) * P * P);
 }
 
-template <int P>
+template <int P, bool EVAL>
 __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomOut o)
 {
     using TL = Tile<P>;
     constexpr int NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY;
     constexpr int NPS = GeomPlanes<P>::NPS;
     constexpr int NYX = NY * NX, TYX = TY * NX;
+    constexpr int NFL = EVAL ? 4 : 3;          // fields: the 3 coordinates of the control points (and u)
     extern __shared__ double smem[];
-    double *cw = smem;                         // [3][P][NY][NX] control points
-    double *sa = cw + 3 * P * NYX;             // [NPS][6][NY][NX]   B3 c, D3 c at g3
-    double *sb = sa + 6 * NPS * NYX;           // [NPS][9][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
-    double *t1B = sb + 9 * NPS * TYX, *t1D = t1B + TL::E1 * P * P;   // tile tables [elem][g][j]
+    double *cw = smem;                         // [NFL][P][NY][NX] control points (and u)
+    double *sa = cw + NFL * P * NYX;           // [NPS][2 NFL][NY][NX]   B3 c, D3 c at g3
+    double *sb = sa + 2 * NFL * NPS * NYX;     // [NPS][3 NFL][TY][NX]   B2 B3 c, D2 B3 c, B2 D3 c
+    double *t1B = sb + 3 * NFL * NPS * TYX, *t1D = t1B + TL::E1 * P * P;   // tile tables [elem][g][j]
     double *t2B = t1D + TL::E1 * P * P, *t2D = t2B + TL::E2 * P * P;
 
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
@@ -95,13 +106,16 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
     const int tid = threadIdx.x;
     const bool f32 = o.prec == Prec::F32;
 
-    for (int idx = tid; idx < 3 * P * NYX; idx += TL::NT) {
+    for (int idx = tid; idx < NFL * P * NYX; idx += TL::NT) {
         int lx = idx % NX, r = idx / NX;
         int ly = r % NY; r /= NY;
         int s3 = r % P, c = r / P;
         int n0 = e1b + lx, n1 = e2b + ly, n2 = e3 + s3;
         double v = 0.0;
-        if (n0 < d0.N && n1 < d1.N) v = pv.ctrl[((int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2)) * 3 + c];
+        if (n0 < d0.N && n1 < d1.N) {
+            const int64_t n = (int64_t)n0 + (int64_t)d0.N * (n1 + (int64_t)d1.N * n2);
+            v = c < 3 ? pv.ctrl[n * 3 + c] : o.u[n];
+        }
         cw[idx] = v;
     }
     {
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
             const int g3 = g3b + gg;
             const double *b3 = d2.B + ((int64_t)e3 * P + g3) * P;
             const double *db3 = d2.D + ((int64_t)e3 * P + g3) * P;
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NFL; ++c) {
                 double a = 0.0, b = 0.0;
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
@@ -141,8 +155,8 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
                     a += b3[s] * v;
                     b += db3[s] * v;
                 }
-                sa[(gg * 6 + c) * NYX + idx] = a;
-                sa[(gg * 6 + 3 + c) * NYX + idx] = b;
+                sa[(gg * 2 * NFL + c) * NYX + idx] = a;
+                sa[(gg * 2 * NFL + NFL + c) * NYX + idx] = b;
             }
         }
         __syncthreads();
@@ -154,14 +168,14 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
             if (ee2 >= d1.K) continue;
             const double *b2 = t2B + (l2 * P + h2) * P;
             const double *db2 = t2D + (l2 * P + h2) * P;
-            const double *sg = sa + gg * 6 * NYX;
-            double *so = sb + gg * 9 * TYX;
-            for (int c = 0; c < 3; ++c) {
+            const double *sg = sa + gg * 2 * NFL * NYX;
+            double *so = sb + gg * 3 * NFL * TYX;
+            for (int c = 0; c < NFL; ++c) {
                 double vb = 0.0, vd = 0.0, wb = 0.0;
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
                     double a = sg[(c * NY + l2 + s) * NX + lx];
-                    double b = sg[((3 + c) * NY + l2 + s) * NX + lx];
+                    double b = sg[((NFL + c) * NY + l2 + s) * NX + lx];
                     vb += b2[s] * a;
                     vd += db2[s] * a;
                     wb += b2[s] * b;
@@ -179,9 +193,9 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
             const int q0 = e1 * P + g1, q1 = e2 * P + g2;
             const double w01 = d0.W[q0] * d1.W[q1];
             for (int gg = 0; gg < NPS; ++gg) {
-                const double *sg = sb + gg * 9 * TYX;
-                double G[3], J[3][3];
-                for (int c = 0; c < 3; ++c) {
+                const double *sg = sb + gg * 3 * NFL * TYX;
+                double G[NFL], J[NFL][3];
+                for (int c = 0; c < NFL; ++c) {
                     double gv = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
 #pragma unroll
                     for (int s = 0; s < P; ++s) {
@@ -201,7 +215,8 @@ __global__ __launch_bounds__(Tile<P>::NT) void geom3d_kernel(PatchView pv, GeomO
                 const int q2 = e3 * P + g3b + gg;
                 const double w = w01 * d2.W[q2];
                 const int64_t qlin = (int64_t)q0 + (int64_t)d0.Q * (q1 + (int64_t)d1.Q * q2);
-                pointwise_3d(G, J, w, qlin, q0, q1, q2, pv, o, f32);
+                const double uh[4] = {G[NFL - 1], J[NFL - 1][0], J[NFL - 1][1], J[NFL - 1][2]};   // u, grad_hat u
+                pointwise_3d(G, J, w, qlin, q0, q1, q2, pv, o, f32, EVAL ? uh : nullptr);
             }
         }
         __syncthreads();
@@ -219,22 +234,32 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
     int q0 = (int)(q % d0.Q), q1 = (DIM == 2) ? (int)(q / d0.Q) : 0;
     int e0 = q0 / P, g0 = q0 % P, e1 = q1 / P, g1 = q1 % P;
     double G[2] = {0, 0}, J[2][2] = {{0, 0}, {0, 0}};
+    double U = 0.0, UG[2] = {0, 0};                // u and grad_hat u (evaluation)
     const double *b0 = d0.B + ((int64_t)e0 * P + g0) * P, *db0 = d0.D + ((int64_t)e0 * P + g0) * P;
     if (DIM == 1) {
         for (int s = 0; s < P; ++s) {
             double c = pv.ctrl[e0 + s];
             G[0] += b0[s] * c;
             J[0][0] += db0[s] * c;
+            if (o.u) {
+                U += b0[s] * o.u[e0 + s];
+                UG[0] += db0[s] * o.u[e0 + s];
+            }
         }
     } else {
         const double *b1 = d1.B + ((int64_t)e1 * P + g1) * P, *db1 = d1.D + ((int64_t)e1 * P + g1) * P;
         for (int s1 = 0; s1 < P; ++s1) {
-            double t0[2] = {0, 0}, t1[2] = {0, 0};
+            double t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};     // coordinates, then u
             for (int s0 = 0; s0 < P; ++s0) {
-                const double *c = pv.ctrl + ((int64_t)(e0 + s0) + (int64_t)d0.N * (e1 + s1)) * 2;
+                const int64_t n = (int64_t)(e0 + s0) + (int64_t)d0.N * (e1 + s1);
+                const double *c = pv.ctrl + n * 2;
                 for (int i = 0; i < 2; ++i) {
                     t0[i] += b0[s0] * c[i];
                     t1[i] += db0[s0] * c[i];
+                }
+                if (o.u) {
+                    t0[2] += b0[s0] * o.u[n];
+                    t1[2] += db0[s0] * o.u[n];
                 }
             }
             for (int i = 0; i < 2; ++i) {
@@ -242,6 +267,9 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
                 J[i][0] += b1[s1] * t1[i];
                 J[i][1] += db1[s1] * t0[i];
             }
+            U += b1[s1] * t0[2];
+            UG[0] += b1[s1] * t1[2];
+            UG[1] += db1[s1] * t0[2];
         }
     }
     double det, inv[2][2];
@@ -261,6 +289,13 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
     const bool f32 = o.prec == Prec::F32;
     if (o.xyz)
         for (int i = 0; i < DIM; ++i) o.xyz[q * DIM + i] = G[i];
+    if (o.u && o.uval) o.uval[q] = U;
+    if (o.u && o.ugrad)
+        for (int i = 0; i < DIM; ++i) {
+            double g = 0.0;
+            for (int k = 0; k < DIM; ++k) g += inv[k][i] * UG[k];     // J^-T grad_hat u
+            o.ugrad[q * DIM + i] = g;
+        }
     if (o.c_mass) {
         double v = wd * eval_coef(o.coef_mass, G, DIM, q);
         int64_t idx = coef_index(DIM, 1, 0, q0, q1, 0, d0.Q, d1.Q);
@@ -279,16 +314,24 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
     }
 }
 
+template <int P, bool EVAL>
+static hipError_t launch_geom3d(const PatchView &pv, const GeomOut &o, hipStream_t s)
+{
+    using TL = Tile<P>;
+    dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
+    constexpr size_t lds = geom3d_lds<P, EVAL>();
+    hipError_t e = allow_dynamic_lds((const void *)geom3d_kernel<P, EVAL>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((geom3d_kernel<P, EVAL>), grid, dim3(TL::NT), lds, s, pv, o);
+    return hipGetLastError();
+}
+
 template <int P>
 static hipError_t launch_geom_p(const PatchView &pv, const GeomOut &o, hipStream_t s)
 {
     if (pv.d == 3) {
-        using TL = Tile<P>;
-        dim3 grid((pv.dir[0].K + TL::E1 - 1) / TL::E1, (pv.dir[1].K + TL::E2 - 1) / TL::E2, pv.dir[2].K);
-        constexpr size_t lds = geom3d_lds<P>();
-        hipError_t e = allow_dynamic_lds((const void *)geom3d_kernel<P>, lds);
+        hipError_t e = o.u ? launch_geom3d<P, true>(pv, o, s) : launch_geom3d<P, false>(pv, o, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(geom3d_kernel<P>, grid, dim3(TL::NT), lds, s, pv, o);
     } else {
         int64_t nb = (pv.Q + 255) / 256;
         if (pv.d == 2)

@@ -62,8 +62,12 @@ struct GeomOut {
     void *c_stiff;         // [Q][ncomp], or null
     double *xyz;           // [Q][d] physical quadrature points, or null
     Coef coef_mass, coef_stiff;
-    int *bad_det;          // device flag set to 1 if det J <= 0 somewhere
+    int *bad_det;          // device flag set to 1 if det J <= 0 somewhere, or null
     Prec prec;
+    // evaluation of a discrete function u = sum_n u_n phi_n (Algorithm 3):
+    const double *u;       // [N] coefficients, or null (no evaluation)
+    double *uval;          // [Q] u at the quadrature points, or null
+    double *ugrad;         // [Q][d] physical gradient J^-T grad_hat u, or null
 };
 
 // Quadrature-coefficient tensor layout: C[q_d][comp][q_{d-1}]..[q_1]

@@ -349,6 +349,23 @@ sf_status sf_patch_quad_points(sf_patch *p, double *dev_xyz)
     return SF_OK;
 }
 
+sf_status sf_patch_eval(sf_patch *p, const double *dev_u, double *dev_val, double *dev_grad)
+{
+    if (!p) return SF_EINVAL;
+    p->ctx->err.clear();
+    if (!dev_u || (!dev_val && !dev_grad)) return fail(p->ctx, SF_EINVAL, "null input or no output");
+    GeomOut o{};
+    o.bad_det = nullptr;          // the det J record belongs to the prepares
+    o.prec = Prec::F64;
+    o.coef_mass = o.coef_stiff = Coef{0, 1.0, nullptr};
+    o.u = dev_u;
+    o.uval = dev_val;
+    o.ugrad = dev_grad;
+    hipError_t e = launch_geometry(p->view, o, p->ctx->stream);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "evaluation kernel");
+    return SF_OK;
+}
+
 // Geometry step.  sync: clear the det J flag, run, read the flag back and
 // report it.  Otherwise only the kernel is queued; the flag keeps any det J <= 0
 // seen since the last sf_patch_geometry_check, which reads and clears it.

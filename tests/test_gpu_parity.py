@@ -756,3 +756,40 @@ def test_error_paths():
     with pytest.raises(sf.SfError) as e:
         GpuPatch(bad, 3, ctrl)
     assert e.value.status == sf.SF_EKNOT
+
+
+@pytest.mark.parametrize("K,p", [((5, 3, 4), 2), ((7, 5, 3), 3), ((20, 3, 2), 4), ((3, 4, 2), 6), ((2, 2, 1), 9),
+                                 ((6,), 4), ((4, 5), 3)])
+def test_eval_values_and_gradients(K, p):
+    """sf_patch_eval (Algorithm 3 on the tensor grid of points, with the
+    geometry's Jacobian in the same pass) against the oracle's plain sums
+    over each point's active functions: values, physical gradients; and a
+    linear physical function reproduced exactly (value and gradient)."""
+    import torch
+    d = len(K)
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=15)
+    P = oracle.Problem(kn, p, ctrl)
+    u = inputs.random_vector(P.N, 16)
+    v_o, g_o, x_o = P.eval(u)
+    with GpuPatch(kn, p, ctrl) as g:
+        ud = torch.as_tensor(u).cuda()
+        val = torch.full((g.Q,), float("nan"), dtype=torch.float64, device="cuda")
+        grad = torch.full((g.Q, d), float("nan"), dtype=torch.float64, device="cuda")
+        sf.sf_patch_eval(ctx(), g.h, ud, val, grad)
+        torch.cuda.synchronize()
+        ev = float(np.abs(val.cpu().numpy() - v_o).max() / np.abs(v_o).max())
+        eg = float(np.abs(grad.cpu().numpy() - g_o).max() / np.abs(g_o).max())
+        record("err_eval", sf.SF_FP64, max(ev, eg))
+        assert ev <= TOL64 and eg <= TOL64, (ev, eg)
+        # linear physical function gamma . x + beta: value and gradient exact
+        gam = np.linspace(-0.8, 1.1, d)
+        ul = torch.as_tensor(np.ascontiguousarray(ctrl.reshape(-1, d) @ gam + 0.5)).cuda()
+        sf.sf_patch_eval(ctx(), g.h, ul, val, grad)
+        torch.cuda.synchronize()
+        assert np.abs(val.cpu().numpy() - (x_o @ gam + 0.5)).max() < 1e-12
+        assert np.abs(grad.cpu().numpy() - gam[None, :]).max() < 1e-11
+        # the physical points agree with sf_patch_quad_points
+        xyz = torch.empty((g.Q, d), dtype=torch.float64, device="cuda")
+        sf.sf_patch_quad_points(ctx(), g.h, xyz)
+        torch.cuda.synchronize()
+        assert np.abs(xyz.cpu().numpy() - x_o).max() < 1e-14

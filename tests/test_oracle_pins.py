@@ -379,3 +379,46 @@ def test_invalid_knots_rejected():
         oracle.tables_1d(np.array([0, 0, 0.5, 1, 1, 1.0]), 3)     # not open at the left
     with pytest.raises(oracle.OracleError):
         oracle.tables_1d(np.array([0, 0, 0, 0.7, 0.5, 1, 1, 1.0]), 3)
+
+
+# ------------------------------------------------------------ evaluation (Algorithm 3)
+
+@pytest.mark.parametrize("d,K,p", [(2, (4, 5), 3), (3, (3, 2, 4), 2), (3, (2, 3, 2), 4), (1, (6,), 5)])
+def test_eval_reproduces_linear_physical_functions(d, K, p):
+    """u_n = gamma . c_n + beta is, by partition of unity and linear
+    precision of G = sum c_n phi_n, the function gamma . x + beta of the
+    physical point: value gamma . G(xhat) + beta, physical gradient gamma, in
+    any (valid) geometry.  A transposed inverse Jacobian or a dropped term
+    changes the gradient."""
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=5)
+    P = oracle.Problem(kn, p, ctrl)
+    rng = np.random.default_rng(3)
+    gam = rng.uniform(-1, 1, d)
+    beta = 0.37
+    v, g, x = P.eval(ctrl.reshape(-1, d) @ gam + beta)
+    assert np.abs(v - (x @ gam + beta)).max() < 1e-13
+    assert np.abs(g - gam[None, :]).max() < 1e-12
+
+
+@pytest.mark.parametrize("K,p", [((3, 2, 4), 3), ((2, 2, 2), 5)])
+def test_eval_values_against_scipy_tensor_product(K, p):
+    """Values of u = sum u_n phi_n at the Gauss points equal the tensor
+    product of scipy B-spline design matrices (an independent evaluation of
+    the basis) applied to u; the physical points agree with the same
+    contraction of the control points."""
+    from scipy.interpolate import BSpline
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=6)
+    P = oracle.Problem(kn, p, ctrl)
+    u = np.random.default_rng(4).uniform(-1, 1, P.N)
+    v, _, x = P.eval(u)
+    # 1D design matrices at the Gauss points of every element, points in order
+    mats = []
+    for k in range(3):
+        xs = oracle.tables_1d(kn[k], p)["x"].ravel()
+        mats.append(BSpline.design_matrix(xs, kn[k], p - 1).toarray())
+    U = u.reshape(P.nfun[2], P.nfun[1], P.nfun[0])        # [i3][i2][i1]
+    ref = np.einsum("ai,bj,ck,kji->cba", mats[0], mats[1], mats[2], U).ravel()
+    assert np.abs(v - ref).max() < 1e-13
+    X = ctrl.reshape(P.nfun[2], P.nfun[1], P.nfun[0], 3)
+    refx = np.einsum("ai,bj,ck,kjid->cbad", mats[0], mats[1], mats[2], X).reshape(-1, 3)
+    assert np.abs(x - refx).max() < 1e-13

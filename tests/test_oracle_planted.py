@@ -19,6 +19,7 @@ PIN_CASES = [
     ("dense brute force 2D", lambda: pins.test_dense_bruteforce_algebraic_form(2, (3, 4), 2, ("sinprod", 0.5))),
     ("dense brute force 3D", lambda: pins.test_dense_bruteforce_algebraic_form(3, (2, 3, 2), 3, ("sinprod", 0.5))),
     ("identity Kronecker", lambda: pins.test_identity_geometry_is_kronecker(2, (5, 4), 3)),
+    ("linear functions, evaluation", lambda: pins.test_eval_reproduces_linear_physical_functions(3, (3, 2, 4), 2)),
 ]
 
 
