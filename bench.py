@@ -118,10 +118,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched"], default="large",
+    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched", "order"], default="large",
                     help="large: d=3 128^3 order 6, geometry + pattern + assembly + 100 applies per step (the "
                          "headline line); single: 48^3 order 4 with one apply; sweep: matrix-free apply at "
-                         "N = 126^3 for orders 2..9; batched: 512 patches")
+                         "N = 126^3 for orders 2..9; batched: 512 patches; order: stiffness assembly of "
+                         "anisotropic patches in the given and the relabelled contraction order")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="precision of the timed step (default fp64; sweep and batched: see their help)")
     ap.add_argument("--mixed-steps", type=int, default=3,
@@ -154,6 +155,8 @@ def main():
         return run_sweep(args)
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "order":
+        return run_order(args)
     return run_patch(args)
 
 
@@ -453,6 +456,53 @@ def run_sweep(args):
                 flush=True)
         sf.sf_patch_destroy(h)
         del x, y
+        torch.cuda.empty_cache()
+    sf.sf_ctx_destroy(ctx)
+
+
+def run_order(args):
+    """Stiffness assembly (FP64) of anisotropic patches with the given
+    contraction order (direction 3 last), with the cyclic relabelling that
+    contracts the direction of fewest elements last, and with the tuner's
+    choice; one JSON line per patch."""
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    stream = torch.cuda.current_stream()
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    for K, p in (((16, 128, 128), 4), ((2, 128, 128), 6), ((128, 4, 128), 4), ((128, 128, 16), 4)):
+        w = inputs.workload_3d(K, p)
+        res = {}
+        for policy in ("given", "relabelled", "tune"):
+            os.environ["SFIGA_ASSEMBLY_ORDER"] = policy
+            h = sf.sf_patch_create(ctx, 3, p, w["knots"], w["ctrl"])
+            N, nnz, Q = sf.sf_patch_info(h)
+            sf.sf_patch_set_coef(ctx, h, sf.SF_STIFF, sf.SF_COEF_SINPROD, 0.5)
+            sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, sf.SF_FP64)
+            v = torch.empty(nnz, dtype=torch.float64, device="cuda")
+            for _ in range(args.warmup + 1):
+                sf.sf_assemble(ctx, h, sf.SF_STIFF, sf.SF_FP64, val_stiff=v)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                sf.sf_assemble(ctx, h, sf.SF_STIFF, sf.SF_FP64, val_stiff=v)
+            e1.record(stream)
+            e1.synchronize()
+            res[policy] = e0.elapsed_time(e1) / args.steps
+            sf.sf_patch_destroy(h)
+            del v
+        os.environ.pop("SFIGA_ASSEMBLY_ORDER", None)
+        kmin = min(range(3), key=lambda k: K[k])
+        Kr = tuple(K[(k + (kmin + 1) % 3) % 3] for k in range(3))
+        print(json.dumps({
+            "metric": "assembly ms, contraction order", "unit": "ms", "dtype": "f64",
+            "config": {"workload": f"d3_{K[0]}x{K[1]}x{K[2]}_p{p}_stiffness_assembly", "elements": list(K),
+                       "order": p, "nnz": nnz},
+            "ms_given_order": res["given"], "ms_relabelled": res["relabelled"], "ms_tuned": res["tune"],
+            "relabelled_elements": list(Kr),
+            "algorithmic_flops_given": assembly_flops(K, p, "stiff"),
+            "algorithmic_flops_relabelled": assembly_flops(Kr, p, "stiff")}), flush=True)
         torch.cuda.empty_cache()
     sf.sf_ctx_destroy(ctx)
 

@@ -141,6 +141,11 @@ hipError_t launch_geometry(const PatchView &pv, const GeomOut &out, hipStream_t 
 hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
                           int64_t col_base, int64_t nnz_base, hipStream_t s);
 hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
+// Values assembled on `alt`, the d = 3 patch pv with its directions relabelled
+// cyclically (alt direction k = pv direction (k + sh) mod 3), moved into pv's
+// CSR layout (tmp: alt's values, vals: pv's).
+hipError_t launch_gather_cyclic(const PatchView &pv, const PatchView &alt, int sh, const double *tmp, double *vals,
+                                hipStream_t s);
 // op: 1 mass, 2 stiffness; c: coefficient tensor of that op at prec
 // lz: element layers per workgroup in direction 3 (0 = default)
 // rs: per-element reference and scale of the F16S storage (null otherwise)

@@ -159,6 +159,50 @@ hipError_t launch_colind_batch(const TaskList &tl, int P, int nblocks, hipStream
     return hipGetLastError();
 }
 
+// Values of a d = 3 matrix assembled with its directions relabelled
+// cyclically (direction k of the relabelled patch is direction (k + sh) mod 3
+// of this one), moved into this patch's CSR layout: entry (m, n) here is
+// entry (pi(m), pi(n)) there.  One wavefront per row, lanes over its entries
+// (stores contiguous, loads gathered).
+__global__ __launch_bounds__(256) void gather_cyclic_kernel(RowIndex ri, RowIndex rp, int sh,
+                                                            const double *__restrict__ tmp, double *__restrict__ vals,
+                                                            int64_t N)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (row >= N) return;
+    const int lane = threadIdx.x % 64, P = ri.P;
+    int m[3];
+    m[0] = (int)(row % ri.N[0]);
+    m[1] = (int)((row / ri.N[0]) % ri.N[1]);
+    m[2] = (int)(row / ((int64_t)ri.N[0] * ri.N[1]));
+    int lo[3], len[3], mp[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = band_lo(m[k], P);
+        len[k] = band_len(m[k], P, ri.N[k]);
+    }
+    for (int k = 0; k < 3; ++k) mp[k] = m[(k + sh) % 3];
+    const int64_t base = row_start(ri, m[0], m[1], m[2]);
+    const int64_t basep = row_start(rp, mp[0], mp[1], mp[2]);
+    const int total = len[0] * len[1] * len[2];
+    for (int off = lane; off < total; off += 64) {
+        int n[3];
+        n[0] = lo[0] + off % len[0];
+        n[1] = lo[1] + (off / len[0]) % len[1];
+        n[2] = lo[2] + off / (len[0] * len[1]);
+        const int np0 = n[sh % 3], np1 = n[(1 + sh) % 3], np2 = n[(2 + sh) % 3];
+        vals[base + off] = tmp[basep + col_offset(rp, mp[0], mp[1], mp[2], np0, np1, np2)];
+    }
+}
+
+hipError_t launch_gather_cyclic(const PatchView &pv, const PatchView &alt, int sh, const double *tmp, double *vals,
+                                hipStream_t s)
+{
+    if (pv.d != 3) return hipErrorInvalidValue;
+    const int64_t nb = (pv.N + 3) / 4;
+    hipLaunchKernelGGL(gather_cyclic_kernel, dim3((unsigned)nb), dim3(256), 0, s, pv.ri, alt.ri, sh, tmp, vals, pv.N);
+    return hipGetLastError();
+}
+
 __global__ void fill_kernel(double *y, int64_t n, double v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -50,6 +50,16 @@ struct sf_patch {
     int tune_t1[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}}, tune_seg[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int tune_lz[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};   // apply: layers per workgroup
     PatchView view{};
+    // Contraction order of the d = 3 assembly (Algorithm 1 contracts direction
+    // 1 first and direction 3 last): per [op][prec] the cyclic relabelling sh
+    // chosen by the tuner (-1 untuned, 0 the given order, 1 or 2: assembled on
+    // `alt`, whose direction k is direction (k + sh) mod 3 here, then gathered
+    // into this layout through `tmpv`).
+    std::vector<double> knots[3];
+    int order_sh[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    sf_patch *alt = nullptr;
+    int alt_sh = 0;
+    double *tmpv = nullptr;
 };
 
 struct sf_batch {
@@ -151,6 +161,7 @@ void free_patch_memory(sf_patch *p)
     (void)hipFree(p->dctrl);
     (void)hipFree(p->dflag);
     (void)hipFree(p->ws);
+    (void)hipFree(p->tmpv);
     for (auto &a : p->C)
         for (void *c : a) (void)hipFree(c);
     for (float *r : p->rs) (void)hipFree(r);
@@ -226,6 +237,7 @@ sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out
     p->P = desc->order[0];
     for (int k = 0; k < desc->d; ++k) {
         if (!desc->knots[k]) { delete p; return fail(ctx, SF_EINVAL, "null knot vector"); }
+        if (desc->n_knots[k] > 0) p->knots[k].assign(desc->knots[k], desc->knots[k] + desc->n_knots[k]);
         bool unsup = false;
         std::string why = build_tables_1d(desc->knots[k], desc->n_knots[k], p->P, p->t[k], unsup);
         if (!why.empty()) {
@@ -332,6 +344,14 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
     int oi = op == SF_MASS ? 0 : 1;
     p->coef[oi] = c;
     for (bool &r : p->ready[oi]) r = false;
+    if (p->alt) {
+        // quadrature-point values follow this patch's point order: the
+        // relabelled patch cannot take them, so the given order is used
+        p->alt->coef[oi] = c;
+        for (bool &r : p->alt->ready[oi]) r = false;
+        if (c.kind == 2)
+            for (int &o : p->order_sh[oi]) o = o > 0 ? 0 : o;
+    }
     return SF_OK;
 }
 
@@ -432,6 +452,13 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
                 if (geom_storage(m) == gi) p->ready[oi][m] = true;
             if (pi == 3) p->ready[oi][3] = true;
         }
+    // the relabelled patch of a tuned contraction order follows every prepare
+    if (p->alt && pi != 3) {
+        unsigned aops = 0;
+        for (int oi = 0; oi < 2; ++oi)
+            if ((ops & (oi == 0 ? SF_MASS : SF_STIFF)) && p->coef[oi].kind != 2) aops |= oi == 0 ? SF_MASS : SF_STIFF;
+        if (aops) return prepare_impl(p->alt, aops, prec, sync);
+    }
     return SF_OK;
 }
 
@@ -560,17 +587,136 @@ static sf_status tune_assembly(sf_patch *p, int oi, int pi, double *dst)
     return SF_OK;
 }
 
+// One operator in the given order (sh = 0) or on the relabelled patch and
+// gathered back (sh > 0).
+static hipError_t assemble_op(sf_patch *p, int oi, int pi, double *dst, hipStream_t s, int sh)
+{
+    sf_patch *q = sh > 0 ? p->alt : p;
+    const int t1 = q->tune_t1[oi][pi] > 0 ? q->tune_t1[oi][pi] : 0;
+    const int seg = q->tune_seg[oi][pi] > 0 ? q->tune_seg[oi][pi] : 0;
+    hipError_t e = launch_assemble(q->view, oi + 1, asm_prec(pi), q->C[oi][cidx(pi)], sh > 0 ? p->tmpv : dst, q->ws,
+                                   q->ws_bytes, s, t1, seg);
+    if (e == hipSuccess && sh > 0) e = launch_gather_cyclic(p->view, q->view, sh, p->tmpv, dst, s);
+    return e;
+}
+
 static sf_status assemble_into(sf_patch *p, unsigned ops, int pi, double *vm, double *vs, hipStream_t s)
 {
     for (int oi = 0; oi < 2; ++oi) {
         if (!(ops & (oi == 0 ? SF_MASS : SF_STIFF))) continue;
-        double *dst = oi == 0 ? vm : vs;
-        const int t1 = p->tune_t1[oi][pi] > 0 ? p->tune_t1[oi][pi] : 0;
-        const int seg = p->tune_seg[oi][pi] > 0 ? p->tune_seg[oi][pi] : 0;
-        hipError_t e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, p->ws,
-                                       p->ws_bytes, s, t1, seg);
+        const int sh = p->order_sh[oi][pi] > 0 && p->alt ? p->order_sh[oi][pi] : 0;
+        hipError_t e = assemble_op(p, oi, pi, oi == 0 ? vm : vs, s, sh);
         if (e != hipSuccess) return hip_fail(p->ctx, e, "assembly kernel");
     }
+    return SF_OK;
+}
+
+// The patch with its directions relabelled cyclically by sh (direction k of
+// the new patch is direction (k + sh) mod 3 here): knots and control points
+// reordered, coordinates unchanged.  A cyclic relabelling is an even
+// permutation of the reference axes, so det J keeps its sign.
+static sf_status make_alt(sf_patch *p, int sh)
+{
+    if (p->alt) return p->alt_sh == sh ? SF_OK : fail(p->ctx, SF_EINVAL, "another contraction order exists");
+    sf_ctx *ctx = p->ctx;
+    const int64_t N = p->view.N;
+    std::vector<double> c(N * 3), ca(N * 3);
+    hipError_t e = hipMemcpyAsync(c.data(), p->dctrl, sizeof(double) * N * 3, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "control points for the relabelled patch");
+    int na[3];
+    for (int k = 0; k < 3; ++k) na[k] = p->t[(k + sh) % 3].nfun;
+    for (int64_t n = 0; n < N; ++n) {
+        const int i[3] = {(int)(n % p->t[0].nfun), (int)((n / p->t[0].nfun) % p->t[1].nfun),
+                          (int)(n / ((int64_t)p->t[0].nfun * p->t[1].nfun))};
+        const int64_t na_idx = i[sh % 3] + (int64_t)na[0] * (i[(1 + sh) % 3] + (int64_t)na[1] * i[(2 + sh) % 3]);
+        for (int x = 0; x < 3; ++x) ca[na_idx * 3 + x] = c[n * 3 + x];
+    }
+    sf_patch_desc d{};
+    d.d = 3;
+    for (int k = 0; k < 3; ++k) {
+        d.order[k] = p->P;
+        d.n_knots[k] = (int64_t)p->knots[(k + sh) % 3].size();
+        d.knots[k] = p->knots[(k + sh) % 3].data();
+    }
+    d.ctrl = ca.data();
+    d.ctrl_on_device = 0;
+    sf_patch *a = nullptr;
+    sf_status st = sf_patch_create(ctx, &d, &a);
+    if (st != SF_OK) return st;
+    a->coef[0] = p->coef[0];
+    a->coef[1] = p->coef[1];
+    e = hipMalloc((void **)&p->tmpv, sizeof(double) * (size_t)p->view.nnz);
+    if (e != hipSuccess) {
+        p->tmpv = nullptr;
+        sf_patch_destroy(a);
+        return hip_fail(ctx, e, "values of the relabelled patch");
+    }
+    p->alt = a;
+    p->alt_sh = sh;
+    return SF_OK;
+}
+
+// SFIGA_ASSEMBLY_ORDER: "given" keeps direction 3 last, "relabelled" always
+// takes the relabelled order, anything else (default) times both.
+static int order_policy()
+{
+    const char *v = getenv("SFIGA_ASSEMBLY_ORDER");
+    if (v && !strcmp(v, "given")) return 0;
+    if (v && !strcmp(v, "relabelled")) return 1;
+    return 2;
+}
+
+// Contraction-order autotuning (the narrow direction contracted last, Sec.
+// 4.2): the level-2 and level-3 costs of Algorithm 1 multiply the 1D band
+// sizes of the directions contracted first, and a direction with few elements
+// has a large band per point (nnz1(N)/Q is p for one element, about 2 - 1/p
+// for many).  Candidates: the given order and the cyclic relabelling that
+// puts the direction with the fewest elements last; each timed (with the
+// gather) on this patch into dst, the faster kept.
+static sf_status tune_order(sf_patch *p, int oi, int pi, double *dst)
+{
+    p->order_sh[oi][pi] = 0;
+    if (p->d != 3 || p->coef[oi].kind == 2 || order_policy() == 0) return SF_OK;
+    int kmin = 2;
+    for (int k = 0; k < 3; ++k)
+        if (p->t[k].nel < p->t[kmin].nel) kmin = k;
+    const int sh = (kmin + 1) % 3;          // relabelled direction 2 is direction kmin
+    if (sh == 0) return SF_OK;
+    if (p->alt && p->alt_sh != sh) return SF_OK;
+    sf_status st = make_alt(p, sh);
+    if (st != SF_OK) return st;
+    sf_patch *a = p->alt;
+    const unsigned bit = oi == 0 ? SF_MASS : SF_STIFF;
+    if (!a->ready[oi][pi]) {
+        st = prepare_impl(a, bit, pi == 0 ? SF_FP64 : (pi == 1 ? SF_FP32 : SF_BF16_SPLIT), true);
+        if (st != SF_OK) return st;
+    }
+    st = ensure_workspace(a);
+    if (st == SF_OK && a->tune_t1[oi][pi] < 0) st = tune_assembly(a, oi, pi, p->tmpv);
+    if (st != SF_OK) return st;
+    if (order_policy() == 1) {
+        p->order_sh[oi][pi] = sh;
+        return SF_OK;
+    }
+    hipStream_t s = p->ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms[2] = {0.f, 0.f};
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        const int shc = c == 0 ? 0 : sh;
+        e = assemble_op(p, oi, pi, dst, s, shc);            // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = assemble_op(p, oi, pi, dst, s, shc);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[c], e0, e1);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "contraction-order autotuning");
+    p->order_sh[oi][pi] = ms[1] < ms[0] ? sh : 0;
     return SF_OK;
 }
 
@@ -587,6 +733,7 @@ sf_status sf_assemble(sf_patch *p, unsigned ops, sf_precision prec, double *vm, 
     for (int oi = 0; oi < 2; ++oi)
         if ((ops & (oi == 0 ? SF_MASS : SF_STIFF)) && p->tune_t1[oi][pi] < 0) {
             st = tune_assembly(p, oi, pi, oi == 0 ? vm : vs);
+            if (st == SF_OK) st = tune_order(p, oi, pi, oi == 0 ? vm : vs);
             if (st != SF_OK) return st;
         }
     return assemble_into(p, ops, pi, vm, vs, p->ctx->stream);
@@ -681,6 +828,7 @@ void sf_patch_destroy(sf_patch *p)
 {
     if (!p) return;
     (void)hipStreamSynchronize(p->ctx->stream);
+    sf_patch_destroy(p->alt);
     free_patch_memory(p);
     delete p;
 }
