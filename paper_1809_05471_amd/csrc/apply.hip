@@ -57,6 +57,9 @@ struct STile {
 //          fetched per apply).  It pays where the kernel waits on HBM (low
 //          orders); from order 5 on the kernel waits on LDS and barriers and
 //          the remap costs 2-6%.
+//   JU, FU with UNRJ = 0, the unroll counts of that loop and of the field loop
+//          of backward direction 1 (two output chains at a time: FP64 order 6
+//          7.94 -> 7.60 ms at 128^3, order 9 46.3 -> 42.7 ms at 118^3);
 //   W      minimum resident waves per SIMD asked of the compiler (register cap).
 // Measured at 128^3 order 6 FP64 (ms per apply): 12.43 before the x-row and
 // table prefetch and the parallel backward direction 3, 11.06 after, 7.95
@@ -64,6 +67,8 @@ struct STile {
 // cost the second workgroup per CU there (16.6).
 struct ApplyShape {
     int G, CMODE, TWOSTEP, UNRJ, W, XCD;
+    int JU = 1;            // with UNRJ = 0: unroll count of the per-element output loops
+    int FU = 1;            // with UNRJ = 0: unroll count of the field loop of backward direction 1
 };
 
 // storage: 0 FP64, 1 FP32, 2 FP16 split
@@ -75,7 +80,9 @@ constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
     if (f64) {
         if (P <= 4) return ApplyShape{1, P == 4 ? 1 : 0, 1, 1, 1, 0};
         if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
-        return ApplyShape{1, 0, 1, 0, 1, 0};
+        if (P == 5) return ApplyShape{1, 0, 1, 0, 1, 0, 2, 3};
+        if (P == 7) return ApplyShape{1, 0, 1, 0, 1, 0, 1, 3};
+        return ApplyShape{1, 0, 1, 0, 1, 0, 2, 1};
     }
     if (storage == 2) return ApplyShape{1, P == 2 ? 2 : (P == 8 ? 1 : 0), P >= 5, 1, 1, P <= 4};
     if (P == 4) return ApplyShape{1, 0, 0, 1, 1, 1};
@@ -91,6 +98,7 @@ struct ApplyCfg {
     static constexpr int CMODE = S.CMODE;
     static constexpr bool TWOSTEP = S.TWOSTEP != 0;
     static constexpr bool UNRJ = S.UNRJ != 0;
+    static constexpr int JU = S.JU, FU = S.FU;
     static constexpr int W = S.W;
     static constexpr bool XCD = S.XCD != 0;
 };
@@ -397,14 +405,14 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CS *__r
                         // one field at a time, one output at a time: its p values are
                         // read before any is overwritten, and only p table values are
                         // live at once
-#pragma unroll 1
+#pragma unroll (CF::FU)
                         for (int f = 0; f < NF; ++f) {
                             const CT *T = (STIFF && f == 0) ? t1D : t1B;
                             CT *col = sh + f * PG * TY * TX + col0;
                             CT v[P];
 #pragma unroll
                             for (int hh = 0; hh < P; ++hh) v[hh] = col[hh];
-#pragma unroll 1
+#pragma unroll (CF::JU)
                             for (int j = 0; j < P; ++j) {
                                 CT part = CT(0);
 #pragma unroll
@@ -504,7 +512,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CS *__r
                             v0[hh] = sr[row0 + hh * NX];
                             v1[hh] = STIFF ? sr[1 * PG * TY * NX + row0 + hh * NX] : CT(0);
                         }
-#pragma unroll 1
+#pragma unroll (CF::JU)
                         for (int j = 0; j < P; ++j) {
                             CT pB = CT(0);
 #pragma unroll
@@ -519,7 +527,7 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CS *__r
                         CT v2[P];
 #pragma unroll
                         for (int hh = 0; hh < P; ++hh) v2[hh] = sr[(NF - 1) * PG * TY * NX + row0 + hh * NX];
-#pragma unroll 1
+#pragma unroll (CF::JU)
                         for (int j = 0; j < P; ++j) {
                             CT pD = CT(0);
 #pragma unroll
