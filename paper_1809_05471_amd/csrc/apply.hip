@@ -69,6 +69,7 @@ struct ApplyShape {
     int G, CMODE, TWOSTEP, UNRJ, W, XCD;
     int JU = 1;            // with UNRJ = 0: unroll count of the per-element output loops
     int FU = 1;            // with UNRJ = 0: unroll count of the field loop of backward direction 1
+    int ROWS = 0;          // the element-row form (apply3d_rows_block); G, CMODE, TWOSTEP, UNRJ, JU, FU unused
 };
 
 // storage: 0 FP64, 1 FP32, 2 FP16 split
@@ -82,6 +83,7 @@ constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
         if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
         if (P == 5) return ApplyShape{1, 0, 1, 0, 1, 0, 2, 3};
         if (P == 7) return ApplyShape{1, 0, 1, 0, 1, 0, 1, 3};
+        if (P == 6) return ApplyShape{1, 2, 1, 0, 4, 1, 1, 1, 1};
         return ApplyShape{1, 0, 1, 0, 1, 0, 2, 1};
     }
     if (storage == 2) return ApplyShape{1, P == 2 ? 2 : (P == 8 ? 1 : 0), P >= 5, 1, 1, P <= 4};
@@ -101,6 +103,7 @@ struct ApplyCfg {
     static constexpr int JU = S.JU, FU = S.FU;
     static constexpr int W = S.W;
     static constexpr bool XCD = S.XCD != 0;
+    static constexpr bool ROWS = S.ROWS != 0;
 };
 
 // Storage of the coefficient tensor: double or float (computed in that type),
@@ -602,6 +605,554 @@ __device__ __forceinline__ void apply3d_block(const PatchView &pv, const CS *__r
     for (int r = 1; r < P; ++r) flush_yrow(e3z + r);
 }
 
+// Tables read by a whole wavefront at one address: through the constant
+// address space the compiler turns these reads into scalar loads, so an
+// element's tables cost neither LDS traffic nor vector registers.
+template <typename T>
+using uniform_ptr = const __attribute__((address_space(4))) T *;
+
+template <typename CT> __device__ __forceinline__ const CT *table_B(const Dir &d);
+template <typename CT> __device__ __forceinline__ const CT *table_D(const Dir &d);
+template <> __device__ __forceinline__ const double *table_B<double>(const Dir &d) { return d.B; }
+template <> __device__ __forceinline__ const double *table_D<double>(const Dir &d) { return d.D; }
+template <> __device__ __forceinline__ const float *table_B<float>(const Dir &d) { return d.Bf; }
+template <> __device__ __forceinline__ const float *table_D<float>(const Dir &d) { return d.Df; }
+
+// The element's p x p table of direction d as a scalar-load pointer; e is
+// wave-uniform (clamped into range: an element beyond the patch only meets
+// zero values, any finite table gives zero there).
+template <typename CT>
+__device__ __forceinline__ uniform_ptr<CT> elem_table(const CT *base, int e, int K, int PP)
+{
+    e = __builtin_amdgcn_readfirstlane(e < K ? e : K - 1);
+    return (uniform_ptr<CT>)(base + (int64_t)e * PP);
+}
+
+// Thread mappings of the element-row form of the d = 3 apply, for PG planes
+// at a time.  A stage whose items belong to one element (its p x p table)
+// gives every element a whole number of wavefronts: lanes per element are the
+// item count rounded up to 64, so the element index, and with it the table
+// address, is the same across a wavefront.
+template <int P, int PG>
+struct RowsMap {
+    using TL = STile<P>;
+    static constexpr int pad64(int n) { return (n + 63) / 64 * 64; }
+    static constexpr int NXY = TL::NX * TL::NY;
+    static constexpr int R2 = pad64(PG * TL::NX);  // direction-2 stages: (plane, function column) per element row l2
+    static constexpr int R1 = pad64(PG * TL::TY);  // direction-1 stages: (plane, point row) per element l1
+    static constexpr int RXY = pad64(NXY);         // direction-3 stages: function columns per plane group
+    static constexpr int GS = TL::NT / RXY >= P ? P : (TL::NT / RXY >= 1 ? TL::NT / RXY : 1);
+    static constexpr int PG3 = (P + GS - 1) / GS;  // planes (forward) or rows (backward) per group
+};
+
+// LDS of the element-row form, in compute-type elements: x and y windows,
+// the direction-3 results (aliasing the point values when all planes go at
+// once), the direction-2 values and the point values of a plane group, and
+// the direction-3 weights.
+template <int P, bool STIFF, int G>
+constexpr int rows_lds_elems()
+{
+    using TL = STile<P>;
+    constexpr int PG = (P + G - 1) / G, NF = STIFF ? 3 : 1, NA = STIFF ? 2 : 1, NXY = TL::NX * TL::NY;
+    constexpr int SA = NA * P * (NXY | 1), SH = NF * PG * TL::TY * (TL::TX | 1), SB = NF * PG * TL::TY * (TL::NX | 1);
+    return 2 * P * NXY + (G == 1 ? (SA > SH ? SA : SH) : SA + SH) + SB + 2 * P + 4 * P * P;
+}
+
+// Element-row form of the d = 3 apply (same box, window and layer walk as
+// apply3d_block).  Each stage that contracts one direction gives a work item
+// one element's whole 1D slice: it reads the slice's p values once, keeps them
+// in registers and forms all p outputs with the element's table in scalar
+// registers, instead of reading a value and a table entry from LDS for every
+// multiply-add.  Stages per layer (F2 to B2 for each group of PG planes):
+//   F3  a = B3 x, b = D3 x (function column, group of planes)
+//   F2  B2 a, D2 a, B2 b (element row l2: plane, function column)
+//   F1  gradients (element l1: plane, point row)
+//   PW  pointwise product with C (one thread per quadrature column)
+//   B1  per-element transposed sums over an element's points (element l1),
+//       then the sums over the elements that share a function
+//   B2  the same in direction 2 (element row l2), then the sums
+//   B3  the transposed direction-3 sums into the y window (function column,
+//       group of rows)
+template <int P, bool STIFF, typename CS>
+__device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS *__restrict__ C,
+                                                   const float *__restrict__ rs, const double *__restrict__ x,
+                                                   double *__restrict__ y, int LZ, int bx, int by, int bz)
+{
+    using CT = typename ComputeOf<CS>::T;
+    constexpr bool SPLIT = !std::is_same<CS, CT>::value;
+    using TL = STile<P>;
+    using CF = ApplyCfg<P, STIFF, CS>;
+    constexpr int G = CF::G, PG = (P + G - 1) / G;
+    using RM = RowsMap<P, PG>;
+    constexpr int E = TL::E, NX = TL::NX, NY = TL::NY, TX = TL::TX, TY = TL::TY, NT = TL::NT;
+    constexpr int NF = STIFF ? 3 : 1;      // gradient components or value
+    constexpr int NA = STIFF ? 2 : 1;      // forward direction-3 results (B3 x, D3 x)
+    constexpr int NC = STIFF ? 6 : 1;      // coefficient components
+    constexpr int PP = P * P, NXY = NX * NY;
+    // Row strides of the stage buffers, rounded up to an odd number of
+    // elements so that items on consecutive rows fall into different LDS banks.
+    constexpr int AS = NXY | 1, HS = TX | 1, BS = NX | 1;
+    constexpr int SHF = PG * TY * HS;      // one field of the point values of a group
+    constexpr int SBF = PG * TY * BS;      // one field of the direction-2 values of a group
+    constexpr int SA = NA * P * AS, SH = NF * SHF;
+    static_assert(G == 1 || CF::CMODE == 0, "plane groups load their coefficients in the pointwise stage");
+    // LDS: x and y windows [P slots][NY][NX]; ra the forward direction-3
+    // results sa and then the backward direction-2 sums sq, [NA][P][AS]; rh
+    // the point values sh [NF][PG][TY][HS]; rb the forward direction-2
+    // results sb and then the backward direction-1 sums sr, [NF][PG][TY][BS].
+    // With one group ra lies inside rh (sa is dead before sh is written, sh
+    // before sq).
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    CT *xw = reinterpret_cast<CT *>(smem_raw);
+    CT *yw = xw + P * NXY;
+    CT *rh = yw + P * NXY;
+    CT *ra = G == 1 ? rh : rh + SH;
+    CT *rb = rh + (G == 1 ? (SA > SH ? SA : SH) : SA + SH);
+    CT *t3Wb = rb + NF * SBF;              // direction-3 weights, [layer parity][g] (FP16 split)
+    CT *t3s = t3Wb + 2 * P;                // direction-3 tables with CMODE 2, [layer parity][B, D][g][j]
+    static_assert(NXY <= NT, "one prefetched x value per thread");
+
+    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
+    const CT *B1g = table_B<CT>(d0), *D1g = table_D<CT>(d0);
+    const CT *B2g = table_B<CT>(d1), *D2g = table_D<CT>(d1);
+    const CT *B3g = table_B<CT>(d2), *D3g = table_D<CT>(d2);
+    const int e1b = bx * E, e2b = by * E;
+    const int e3a = bz * LZ;
+    const int e3z = (e3a + LZ < d2.K ? e3a + LZ : d2.K) - 1;      // last layer
+    const int Q0 = d0.Q, Q1 = d1.Q;
+    const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
+    const int64_t tile0 = SPLIT ? split_index(NC, 0, e1b * P, e2b * P, 0, P, d0.K, d1.K) : 0;
+    const int64_t plane_stride = SPLIT ? split_index(NC, 1, 0, 0, 0, P, d0.K, d1.K) : 0;
+
+    // Per-thread offsets are recomputed inside each stage from an opaque copy
+    // of the thread index: hoisted out of the layer loop, the offsets of all
+    // stages would hold registers for the whole kernel.
+    auto thread_index = [&]() {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
+    // The thread's quadrature column (pointwise stage).  Loads are issued
+    // without a condition (an inactive thread reads an in-range address, its
+    // results are zeroed where they are stored): under a branch the compiler
+    // waits for every load in flight at the next use of any of them.
+    struct Col {
+        int tid, tx, ty, le1;
+        bool active;
+        int64_t cq0, cq1;
+    };
+    auto column = [&]() {
+        Col c;
+        c.tid = thread_index();
+        c.tx = c.tid % TX;
+        c.ty = c.tid / TX;
+        c.le1 = c.tx / P;
+        c.active = c.tid < TX * TY && e1b + c.le1 < d0.K && e2b + c.ty / P < d1.K;
+        c.cq0 = c.active ? (int64_t)e1b * P + c.tx : 0;
+        c.cq1 = c.active ? (int64_t)e2b * P + c.ty : 0;
+        return c;
+    };
+    auto load_plane = [&](const Col &c, int e3, int g3, CS *dst) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            if constexpr (SPLIT)
+                dst[k] = C[tile0 + ((int64_t)(e3 * P + g3) * NC + k) * plane_stride +
+                           (c.tid < TX * TY ? c.tid : TX * TY - 1)];
+            else
+                dst[k] = C[coef_index(3, NC, k, (int)c.cq0, (int)c.cq1, e3 * P + g3, Q0, Q1)];
+        }
+    };
+    auto flush_yrow = [&](int n3) {          // add the finished row to y and clear its slot
+        for (int idx = thread_index(); idx < NXY; idx += NT) {
+            const int lx = idx % NX, ly = idx / NX;
+            const int n0 = e1b + lx, n1 = e2b + ly;
+            CT *slot = yw + (n3 % P) * NXY + idx;
+            if (n0 < d0.N && n1 < d1.N) atomicAdd(&y[n0 + N0 * n1 + N01 * n3], (double)*slot);
+            *slot = CT(0);
+        }
+    };
+
+    {
+        const int tid = threadIdx.x;
+        for (int i = tid; i < P * NXY; i += NT) yw[i] = CT(0);
+        for (int r = 0; r < P; ++r) {
+            const int n3 = e3a + r;
+            for (int idx = tid; idx < NXY; idx += NT) {
+                const int n0 = e1b + idx % NX, n1 = e2b + idx / NX;
+                xw[(n3 % P) * NXY + idx] = (n0 < d0.N && n1 < d1.N) ? (CT)x[n0 + N0 * n1 + N01 * n3] : CT(0);
+            }
+        }
+        if (SPLIT && tid < P) t3Wb[(e3a & 1) * P + tid] = (CT)d2.W[(int64_t)e3a * P + tid];
+    }
+    // Global loads are issued in the order they are needed (the memory
+    // counter retires in order) and without a condition: the x row that
+    // enters the window after layer e3's forward direction-3 stage (row e3 +
+    // P) and the direction-3 weights of layer e3 + 1, then the coefficients
+    // of layer e3 (CMODE 1 and 2; CMODE 0 loads each group's in its
+    // pointwise stage).  With CMODE 2 they are issued at the end of the
+    // pointwise stage of layer e3 - 1, so that they have a whole layer to
+    // arrive.  Rows and layers past the end are clamped into range; their
+    // values are not used.
+    // With CMODE 2 the direction-3 tables of the next layer come the same way
+    // (into registers, then into LDS during the last stage of the layer), and
+    // the coefficient loads are spread over three stages (planes [0, p/3) at
+    // the end of the pointwise stage, then the rest after backward stages 1
+    // and 2) so that their issue does not stall one stage.
+    constexpr bool T3L = CF::CMODE == 2;
+    double xn, tnW, tnB = 0.0, tnD = 0.0;
+    CS cur[CF::CMODE ? P : PG][NC];
+    auto load_layer_head = [&](int e3) {
+        const int tid = thread_index();
+        const int xlx = tid % NX, xly = tid / NX;
+        const bool xin = tid < NXY && e1b + xlx < d0.N && e2b + xly < d1.N;
+        const int64_t xoff = xin ? (e1b + xlx) + N0 * (e2b + xly) : 0;
+        const int e3c = e3 <= e3z ? e3 : e3z;
+        xn = x[xoff + N01 * (e3c + P < d2.N ? e3c + P : d2.N - 1)];
+        xn = xin ? xn : 0.0;
+        tnW = SPLIT ? d2.W[(int64_t)(e3c < e3z ? e3c + 1 : e3c) * P + (tid % P)] : 0.0;
+        if constexpr (T3L) {
+            const int64_t o = (int64_t)e3c * PP + (tid < PP ? tid : 0);
+            tnB = B3g[o];
+            tnD = D3g[o];
+        }
+    };
+    auto load_planes = [&](int e3, int lo, int hi) {
+        if constexpr (CF::CMODE != 0) {
+            const int e3c = e3 <= e3z ? e3 : e3z;
+            const Col c = column();
+#pragma unroll
+            for (int gl = 0; gl < P; ++gl)
+                if (gl >= lo && gl < hi) load_plane(c, e3c, gl, cur[gl]);
+        }
+    };
+    auto store_t3 = [&](int e3) {          // the direction-3 tables of layer e3, loaded by load_layer_head
+        if constexpr (T3L) {
+            const int tid = thread_index();
+            if (tid < PP) {
+                t3s[(e3 & 1) * 2 * PP + tid] = (CT)tnB;
+                t3s[(e3 & 1) * 2 * PP + PP + tid] = (CT)tnD;
+            }
+        }
+    };
+    if constexpr (CF::CMODE == 2) {
+        load_layer_head(e3a);
+        store_t3(e3a);
+        load_planes(e3a, 0, P);
+    }
+    __syncthreads();
+
+    for (int e3 = e3a; e3 <= e3z; ++e3) {
+        const bool more = e3 < e3z;
+        const CT *t3W = t3Wb + (e3 & 1) * P;
+        if constexpr (CF::CMODE != 2) {
+            load_layer_head(e3);
+            load_planes(e3, 0, P);
+        }
+        // direction-3 tables of this layer: from LDS (CMODE 2) or scalar loads
+        const CT *t3L = t3s + (e3 & 1) * 2 * PP;
+        const uniform_ptr<CT> T3Bs = elem_table(B3g, e3, d2.K, PP), T3Ds = elem_table(D3g, e3, d2.K, PP);
+        auto t3b = [&](int i) -> CT { if constexpr (T3L) return t3L[i]; else return T3Bs[i]; };
+        auto t3d = [&](int i) -> CT { if constexpr (T3L) return t3L[PP + i]; else return T3Ds[i]; };
+
+        // ---- F3: a = B3 x, b = D3 x, per function column and group of planes
+        for (int idx = thread_index(); idx < RM::GS * RM::RXY; idx += NT) {
+            const int grp = __builtin_amdgcn_readfirstlane(idx / RM::RXY), j = idx % RM::RXY;
+            if (j < NXY) {
+                CT v[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) v[s] = xw[((e3 + s) % P) * NXY + j];
+#pragma unroll
+                for (int k = 0; k < RM::PG3; ++k) {
+                    const int g3 = grp * RM::PG3 + k;
+                    if (g3 < P) {
+                        CT a = CT(0), b = CT(0);
+#pragma unroll
+                        for (int s = 0; s < P; ++s) {
+                            a += t3b(g3 * P + s) * v[s];
+                            if (STIFF) b += t3d(g3 * P + s) * v[s];
+                        }
+                        ra[g3 * AS + j] = a;
+                        if (STIFF) ra[(P + g3) * AS + j] = b;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the slot of x row e3 is free now
+        if (more) {
+            const int tid = thread_index();
+            if (tid < NXY) xw[((e3 + P) % P) * NXY + tid] = (CT)xn;
+            if (SPLIT && tid < P) t3Wb[((e3 + 1) & 1) * P + tid] = (CT)tnW;
+        }
+#pragma unroll 1
+        for (int grp = 0; grp < G; ++grp) {
+            const int g0 = grp * PG;
+            const int npl = P - g0 < PG ? P - g0 : PG;          // planes in this group
+            // ---- F2: per element row l2 and (plane, function column): B2 a, D2 a, B2 b at its p points
+            for (int idx = thread_index(); idx < E * RM::R2; idx += NT) {
+                const int l2 = idx / RM::R2, r = idx % RM::R2;
+                const uniform_ptr<CT> T2B = elem_table(B2g, e2b + l2, d1.K, PP);
+                const uniform_ptr<CT> T2D = elem_table(D2g, e2b + l2, d1.K, PP);
+                if (r < npl * NX) {
+                    const int gl = r / NX, lx = r % NX;
+                    CT a[P], b[P];
+#pragma unroll
+                    for (int s = 0; s < P; ++s) {
+                        a[s] = ra[(g0 + gl) * AS + (l2 + s) * NX + lx];
+                        if (STIFF) b[s] = ra[(P + g0 + gl) * AS + (l2 + s) * NX + lx];
+                    }
+                    CT *o = rb + (gl * TY + l2 * P) * BS + lx;
+#pragma unroll
+                    for (int h2 = 0; h2 < P; ++h2) {
+                        CT vb = CT(0), vd = CT(0), wb = CT(0);
+#pragma unroll
+                        for (int s = 0; s < P; ++s) {
+                            vb += T2B[h2 * P + s] * a[s];
+                            if (STIFF) {
+                                vd += T2D[h2 * P + s] * a[s];
+                                wb += T2B[h2 * P + s] * b[s];
+                            }
+                        }
+                        o[h2 * BS] = vb;
+                        if (STIFF) {
+                            o[SBF + h2 * BS] = vd;
+                            o[2 * SBF + h2 * BS] = wb;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- F1, per element l1 and (plane, point row): the gradient (mass:
+            // the value) at the element's p points from the p function values of
+            // each field, into sh
+            for (int idx = thread_index(); idx < E * RM::R1; idx += NT) {
+                const int l1 = idx / RM::R1, r = idx % RM::R1;
+                const uniform_ptr<CT> T1B = elem_table(B1g, e1b + l1, d0.K, PP);
+                const uniform_ptr<CT> T1D = elem_table(D1g, e1b + l1, d0.K, PP);
+                if (r < npl * TY) {
+                    const CT *in = rb + r * BS + l1;         // r = gl * TY + yy; function l1 + s at in[s]
+                    CT *out = rh + r * HS + l1 * P;          // point g1 at out[g1]
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        CT v[P];
+#pragma unroll
+                        for (int s2 = 0; s2 < P; ++s2) v[s2] = in[f * SBF + s2];
+#pragma unroll
+                        for (int g = 0; g < P; ++g) {
+                            CT acc = CT(0);
+#pragma unroll
+                            for (int s2 = 0; s2 < P; ++s2)
+                                acc += ((STIFF && f == 0) ? T1D[g * P + s2] : T1B[g * P + s2]) * v[s2];
+                            out[f * SHF + g] = acc;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- PW: the pointwise coefficient, one thread per quadrature column, in place
+            {
+                const Col c = column();
+                if constexpr (CF::CMODE == 0) {
+#pragma unroll
+                    for (int gl = 0; gl < PG; ++gl) load_plane(c, e3, g0 + gl < P ? g0 + gl : P - 1, cur[gl]);
+                }
+                if (c.tid < TX * TY) {
+                    // FP16 split: the element's reference and scale of this layer
+                    // and the weight of the column in directions 1 and 2
+                    CT rsr[SPLIT ? 2 * NC : 1];
+                    CT w12 = CT(0);
+                    if constexpr (SPLIT) {
+                        const int64_t rs_col =
+                            c.active ? ((int64_t)(e2b + c.ty / P) * d0.K + e1b + c.le1) * 2 * NC : 0;
+#pragma unroll
+                        for (int k = 0; k < 2 * NC; ++k)
+                            rsr[k] = rs[(int64_t)e3 * d1.K * d0.K * 2 * NC + rs_col + k];
+                        w12 = (CT)(d0.W[c.cq0] * d1.W[c.cq1]);
+                    }
+#pragma unroll
+                    for (int gl = 0; gl < PG; ++gl) {
+                        if (gl >= npl) break;
+                        const CS *cr = cur[CF::CMODE ? (G == 1 ? gl : 0) : gl];
+                        CT cg[NC];
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            if constexpr (SPLIT)
+                                cg[k] = w12 * t3W[g0 + gl] * (rsr[2 * k] + rsr[2 * k + 1] * __half2float(cr[k]));
+                            else
+                                cg[k] = (CT)cr[k];
+                        }
+                        CT *pt = rh + (gl * TY + c.ty) * HS + c.tx;
+                        CT h[NF];
+                        if (STIFF) {
+                            const CT gr0 = pt[0], gr1 = pt[SHF], gr2 = pt[2 * SHF];
+                            const CT *q = cg;             // components 00 11 22 01 02 12
+                            h[0] = q[0] * gr0 + q[3] * gr1 + q[4] * gr2;
+                            h[NF > 1 ? 1 : 0] = q[3] * gr0 + q[1] * gr1 + q[5] * gr2;
+                            h[NF > 2 ? 2 : 0] = q[4] * gr0 + q[5] * gr1 + q[2] * gr2;
+                        } else {
+                            h[0] = cg[0] * pt[0];
+                        }
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) pt[f * SHF] = c.active ? h[f] : CT(0);
+                    }
+                }
+            }
+            if constexpr (CF::CMODE == 2) {
+                load_layer_head(e3 + 1);
+                load_planes(e3 + 1, 0, P / 3);
+            }
+            __syncthreads();
+            // ---- B1, per element l1 and (plane, point row): the p transposed sums
+            // over the element's points, written over the element's own p values
+            for (int idx = thread_index(); idx < E * RM::R1; idx += NT) {
+                const int l1 = idx / RM::R1, r = idx % RM::R1;
+                const uniform_ptr<CT> T1B = elem_table(B1g, e1b + l1, d0.K, PP);
+                const uniform_ptr<CT> T1D = elem_table(D1g, e1b + l1, d0.K, PP);
+                if (r < npl * TY) {
+                    CT *col = rh + r * HS + l1 * P;          // r = gl * TY + yy
+                    // one field at a time (field 0 with D for stiffness, the others
+                    // with B), one row of the table (point hh, all functions j) at a time
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        CT v[P], part[P];
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh) {
+                            v[hh] = col[f * SHF + hh];
+                            part[hh] = CT(0);
+                        }
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh)
+#pragma unroll
+                            for (int j = 0; j < P; ++j)
+                                part[j] += ((STIFF && f == 0) ? T1D[hh * P + j] : T1B[hh * P + j]) * v[hh];
+#pragma unroll
+                        for (int j = 0; j < P; ++j) col[f * SHF + j] = part[j];
+                    }
+                }
+            }
+            if constexpr (CF::CMODE == 2) load_planes(e3 + 1, P / 3, 2 * P / 3);
+            __syncthreads();
+            // then per function column lx the sum over the <= p elements that share it
+            for (int idx = thread_index(); idx < npl * TY * NX; idx += NT) {
+                const int lx = idx % NX, rr = idx / NX;          // rr = gl * TY + yy
+                CT rv[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) rv[f] = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l1 = lx - j;                       // element whose local function j is lx
+                    if (l1 < 0 || l1 >= E) continue;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) rv[f] += rh[f * SHF + rr * HS + l1 * P + j];
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) rb[f * SBF + rr * BS + lx] = rv[f];
+            }
+            __syncthreads();
+            // ---- B2, per element row l2 and (plane, function column): the p
+            // transposed sums over the element's points, written over the
+            // element's own rows: the B-part from fields 0 and 1 into field 0,
+            // then the D-part from field 2 into field 1 (each field is read
+            // before it is overwritten)
+            for (int idx = thread_index(); idx < E * RM::R2; idx += NT) {
+                const int l2 = idx / RM::R2, r = idx % RM::R2;
+                const uniform_ptr<CT> T2B = elem_table(B2g, e2b + l2, d1.K, PP);
+                const uniform_ptr<CT> T2D = elem_table(D2g, e2b + l2, d1.K, PP);
+                if (r < npl * NX) {
+                    const int gl = r / NX, lx = r % NX;
+                    CT *o = rb + (gl * TY + l2 * P) * BS + lx;   // point h: o[h BS]
+                    {
+                        CT v0[P], v1[P], pB[P];
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh) {
+                            v0[hh] = o[hh * BS];
+                            if (STIFF) v1[hh] = o[SBF + hh * BS];
+                            pB[hh] = CT(0);
+                        }
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh)
+#pragma unroll
+                            for (int j = 0; j < P; ++j) {
+                                pB[j] += T2B[hh * P + j] * v0[hh];
+                                if (STIFF) pB[j] += T2D[hh * P + j] * v1[hh];
+                            }
+#pragma unroll
+                        for (int j = 0; j < P; ++j) o[j * BS] = pB[j];
+                    }
+                    if constexpr (STIFF) {
+                        CT v[P], pD[P];
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh) {
+                            v[hh] = o[2 * SBF + hh * BS];
+                            pD[hh] = CT(0);
+                        }
+#pragma unroll
+                        for (int hh = 0; hh < P; ++hh)
+#pragma unroll
+                            for (int j = 0; j < P; ++j) pD[j] += T2B[hh * P + j] * v[hh];
+#pragma unroll
+                        for (int j = 0; j < P; ++j) o[SBF + j * BS] = pD[j];
+                    }
+                }
+            }
+            if constexpr (CF::CMODE == 2) load_planes(e3 + 1, 2 * P / 3, P);
+            __syncthreads();
+            // then per function row the sum over the <= p elements that share it, into sq
+            for (int idx = thread_index(); idx < npl * NXY; idx += NT) {
+                const int j2 = idx % NXY, gl = idx / NXY;
+                const int lx = j2 % NX, ly = j2 / NX;
+                CT sB = CT(0), sD = CT(0);
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int l2 = ly - j;
+                    if (l2 < 0 || l2 >= E) continue;
+                    const int row = (gl * TY + l2 * P + j) * BS + lx;
+                    sB += rb[row];
+                    if (STIFF) sD += rb[SBF + row];
+                }
+                ra[(g0 + gl) * AS + j2] = sB;
+                if (STIFF) ra[(P + g0 + gl) * AS + j2] = sD;
+            }
+            __syncthreads();
+        }
+        // ---- B3: per function column and group of rows s3, into the y window
+        for (int idx = thread_index(); idx < RM::GS * RM::RXY; idx += NT) {
+            const int grp = __builtin_amdgcn_readfirstlane(idx / RM::RXY), j = idx % RM::RXY;
+            if (j < NXY) {
+                CT q[NA][P];
+#pragma unroll
+                for (int g3 = 0; g3 < P; ++g3) {
+                    q[0][g3] = ra[g3 * AS + j];
+                    if (STIFF) q[NA - 1][g3] = ra[(P + g3) * AS + j];
+                }
+                CT acc[RM::PG3];
+#pragma unroll
+                for (int k = 0; k < RM::PG3; ++k) acc[k] = CT(0);
+#pragma unroll
+                for (int g3 = 0; g3 < P; ++g3) {
+#pragma unroll
+                    for (int k = 0; k < RM::PG3; ++k) {
+                        const int s3 = grp * RM::PG3 + k < P ? grp * RM::PG3 + k : P - 1;
+                        acc[k] += t3b(g3 * P + s3) * q[0][g3];
+                        if (STIFF) acc[k] += t3d(g3 * P + s3) * q[NA - 1][g3];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < RM::PG3; ++k) {
+                    const int s3 = grp * RM::PG3 + k;
+                    if (s3 < P) yw[((e3 + s3) % P) * NXY + j] += acc[k];
+                }
+            }
+        }
+        if (more) store_t3(e3 + 1);
+        __syncthreads();
+        // ---- row e3 is complete for this box
+        flush_yrow(e3);
+    }
+    __syncthreads();
+    for (int r = 1; r < P; ++r) flush_yrow(e3z + r);
+}
+
 // d = 1, 2: one thread per element, element-local sum factorization,
 // atomics into y.
 
@@ -618,7 +1169,10 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
     // 128-byte lines): on one XCD those lines are fetched once
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     if (ApplyCfgS<P, STIFF, CS>::XCD) xcd_tile(bx, by, bz);
-    apply3d_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
+    if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
+        apply3d_rows_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
+    else
+        apply3d_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
 }
 
 // Persistent form over the concatenated per-patch grids of a batch.
@@ -631,8 +1185,12 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
         const int64_t l = it - tl.off[t];
         const int bx = (int)(l % T.gx);
         const int64_t r = l / T.gx;
-        apply3d_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
-                                    (int)(r / T.gy));
+        if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
+            apply3d_rows_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
+                                             (int)(r / T.gy));
+        else
+            apply3d_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
+                                        (int)(r / T.gy));
         __syncthreads();   // LDS of the next block
     }
 }
@@ -715,6 +1273,7 @@ static size_t apply3d_lds()
     constexpr int PG = (P + CF::G - 1) / CF::G;
     constexpr int SA = 2 * P * NXY, SH = NF * PG * TL::TY * TL::TX, SB = NF * PG * TL::TY * TL::NX;
     constexpr int SAHQ = CF::G == 1 ? (SA > SH ? SA : SH) : 2 * SA + SH;
+    if constexpr (CF::ROWS) return sizeof(CT) * (size_t)rows_lds_elems<P, STIFF, CF::G>();
     return sizeof(CT) * (size_t)(2 * P * NXY + SAHQ + SB + 4 * TL::E * P * P + 4 * P * P + 2 * P);
 }
 

@@ -14,6 +14,8 @@ struct Dir {
     const double *D;   // [K][P][P]: first derivative
     const double *W;   // [K][P]: Gauss weights mapped to the element
     const double *X;   // [K][P]: Gauss points
+    const float *Bf;   // B and D rounded to FP32, for the FP32-computing kernels
+    const float *Df;
     int K, N, Q;       // elements, functions (K+P-1), quadrature points (K*P)
 };
 

@@ -34,6 +34,8 @@ struct sf_patch {
     Tables1D t[3];
     double *dB[3] = {nullptr, nullptr, nullptr}, *dD[3] = {nullptr, nullptr, nullptr};
     double *dW[3] = {nullptr, nullptr, nullptr}, *dX[3] = {nullptr, nullptr, nullptr};
+    float *dBf[3] = {nullptr, nullptr, nullptr}, *dDf[3] = {nullptr, nullptr, nullptr};
+    std::vector<float> Bf[3], Df[3];     // host copies of the FP32 tables (kept for the async upload)
     int64_t *dS[3] = {nullptr, nullptr, nullptr};
     double *dctrl = nullptr;
     int *dflag = nullptr;
@@ -156,6 +158,8 @@ void free_patch_memory(sf_patch *p)
         (void)hipFree(p->dD[k]);
         (void)hipFree(p->dW[k]);
         (void)hipFree(p->dX[k]);
+        (void)hipFree(p->dBf[k]);
+        (void)hipFree(p->dDf[k]);
         (void)hipFree(p->dS[k]);
     }
     (void)hipFree(p->dctrl);
@@ -270,6 +274,12 @@ sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out
             if (e == hipSuccess) e = upload(&p->dD[k], t.D.data(), t.D.size(), s);
             if (e == hipSuccess) e = upload(&p->dW[k], t.w.data(), t.w.size(), s);
             if (e == hipSuccess) e = upload(&p->dX[k], t.x.data(), t.x.size(), s);
+            p->Bf[k].assign(t.B.begin(), t.B.end());
+            p->Df[k].assign(t.D.begin(), t.D.end());
+            if (e == hipSuccess) e = upload(&p->dBf[k], p->Bf[k].data(), p->Bf[k].size(), s);
+            if (e == hipSuccess) e = upload(&p->dDf[k], p->Df[k].data(), p->Df[k].size(), s);
+            dr.Bf = p->dBf[k];
+            dr.Df = p->dDf[k];
             dr.B = p->dB[k];
             dr.D = p->dD[k];
             dr.W = p->dW[k];
