@@ -69,7 +69,8 @@ struct ApplyShape {
     int G, CMODE, TWOSTEP, UNRJ, W, XCD;
     int JU = 1;            // with UNRJ = 0: unroll count of the per-element output loops
     int FU = 1;            // with UNRJ = 0: unroll count of the field loop of backward direction 1
-    int ROWS = 0;          // the element-row form (apply3d_rows_block); G, CMODE, TWOSTEP, UNRJ, JU, FU unused
+    int ROWS = 0;          // the element-row form (apply3d_rows_block); TWOSTEP, UNRJ, JU, FU unused
+    int ALAY = 0;          // with ROWS: the coefficients in the tiled layout of apply_coef_index
 };
 
 // storage: 0 FP64, 1 FP32, 2 FP16 split
@@ -83,7 +84,7 @@ constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
         if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
         if (P == 5) return ApplyShape{1, 0, 1, 0, 1, 0, 2, 3};
         if (P == 7) return ApplyShape{1, 0, 1, 0, 1, 0, 1, 3};
-        if (P == 6) return ApplyShape{1, 2, 1, 0, 4, 1, 1, 1, 1};
+        if (P == 6) return ApplyShape{1, 2, 1, 0, 4, 1, 1, 1, 1, 1};
         return ApplyShape{1, 0, 1, 0, 1, 0, 2, 1};
     }
     if (storage == 2) return ApplyShape{1, P == 2 ? 2 : (P == 8 ? 1 : 0), P >= 5, 1, 1, P <= 4};
@@ -104,6 +105,7 @@ struct ApplyCfg {
     static constexpr int W = S.W;
     static constexpr bool XCD = S.XCD != 0;
     static constexpr bool ROWS = S.ROWS != 0;
+    static constexpr bool ALAY = S.ROWS != 0 && S.ALAY != 0;
 };
 
 // Storage of the coefficient tensor: double or float (computed in that type),
@@ -673,7 +675,7 @@ constexpr int rows_lds_elems()
 //   B2  the same in direction 2 (element row l2), then the sums
 //   B3  the transposed direction-3 sums into the y window (function column,
 //       group of rows)
-template <int P, bool STIFF, typename CS>
+template <int P, bool STIFF, typename CS, bool ALAY>
 __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS *__restrict__ C,
                                                    const float *__restrict__ rs, const double *__restrict__ x,
                                                    double *__restrict__ y, int LZ, int bx, int by, int bz)
@@ -752,7 +754,28 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
         c.cq1 = c.active ? (int64_t)e2b * P + c.ty : 0;
         return c;
     };
+    // tiled layout (ALAY): the tile's block of plane q3, a pair of components
+    // per load
+    constexpr int W = STIFF ? 2 : 1;
+    const int64_t tile_base = (int64_t)(by * ((d0.K + E - 1) / E) + bx) * d2.Q;
     auto load_plane = [&](const Col &c, int e3, int g3, CS *dst) {
+        if constexpr (ALAY && !SPLIT) {
+            const int64_t t = c.tid < TX * TY ? c.tid : TX * TY - 1;
+            const int64_t b0 = (tile_base + e3 * P + g3) * (NC / W) * (TX * TY);
+#pragma unroll
+            for (int kp = 0; kp < NC / W; ++kp) {
+                const CS *src = C + (b0 + kp * (TX * TY) + t) * W;
+                if constexpr (W == 2) {
+                    using V2 = typename std::conditional<sizeof(CS) == 8, double2, float2>::type;
+                    const V2 v = *reinterpret_cast<const V2 *>(src);
+                    dst[2 * kp] = v.x;
+                    dst[2 * kp + 1] = v.y;
+                } else {
+                    dst[kp] = src[0];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             if constexpr (SPLIT)
@@ -1159,7 +1182,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
 template <int P, bool STIFF, typename CS>
 using ApplyCfgS = ApplyCfg<P, STIFF, CS>;
 
-template <int P, bool STIFF, typename CS>
+template <int P, bool STIFF, typename CS, bool ALAY>
 __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void apply3d_kernel(
     PatchView pv, const CS *__restrict__ C, const float *__restrict__ rs, const double *__restrict__ x,
     double *__restrict__ y, int LZ)
@@ -1170,7 +1193,7 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     if (ApplyCfgS<P, STIFF, CS>::XCD) xcd_tile(bx, by, bz);
     if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
-        apply3d_rows_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
+        apply3d_rows_block<P, STIFF, CS, ALAY>(pv, C, rs, x, y, LZ, bx, by, bz);
     else
         apply3d_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
 }
@@ -1186,8 +1209,8 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
         const int bx = (int)(l % T.gx);
         const int64_t r = l / T.gx;
         if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
-            apply3d_rows_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
-                                             (int)(r / T.gy));
+            apply3d_rows_block<P, STIFF, CS, false>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx,
+                                                    (int)(r % T.gy), (int)(r / T.gy));
         else
             apply3d_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
                                         (int)(r / T.gy));
@@ -1292,18 +1315,30 @@ void apply_blocks(const PatchView &pv, int lz, int &gx, int &gy, int &gz, int &L
     gz = (pv.dir[2].K + LZ - 1) / LZ;
 }
 
-template <int P, bool STIFF, typename CS>
-static hipError_t launch_apply_t(const PatchView &pv, const CS *C, const float *rs, const double *x, double *y,
+template <int P, bool STIFF, typename CS, bool ALAY>
+static hipError_t launch_apply3d(const PatchView &pv, const CS *C, const float *rs, const double *x, double *y,
                                  hipStream_t s, int lz)
 {
+    const size_t lds = apply3d_lds<P, STIFF, CS>();
+    hipError_t e = allow_dynamic_lds((const void *)apply3d_kernel<P, STIFF, CS, ALAY>, lds);
+    if (e != hipSuccess) return e;
+    int gx, gy, gz, LZ;
+    apply_blocks(pv, lz, gx, gy, gz, LZ);
+    hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CS, ALAY>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, rs,
+                       x, y, LZ);
+    return hipGetLastError();
+}
+
+template <int P, bool STIFF, typename CS>
+static hipError_t launch_apply_t(const PatchView &pv, const CS *C, const float *rs, const double *x, double *y,
+                                 hipStream_t s, int lz, bool tiled)
+{
     if (pv.d == 3) {
-        const size_t lds = apply3d_lds<P, STIFF, CS>();
-        hipError_t e = allow_dynamic_lds((const void *)apply3d_kernel<P, STIFF, CS>, lds);
-        if (e != hipSuccess) return e;
-        int gx, gy, gz, LZ;
-        apply_blocks(pv, lz, gx, gy, gz, LZ);
-        hipLaunchKernelGGL((apply3d_kernel<P, STIFF, CS>), dim3(gx, gy, gz), dim3(STile<P>::NT), lds, s, pv, C, rs,
-                           x, y, LZ);
+        if constexpr (ApplyCfg<P, STIFF, CS>::ALAY) {
+            if (tiled) return launch_apply3d<P, STIFF, CS, true>(pv, C, rs, x, y, s, lz);
+        }
+        if (tiled) return hipErrorInvalidValue;       // this shape reads the coef_index layout
+        return launch_apply3d<P, STIFF, CS, false>(pv, C, rs, x, y, s, lz);
     } else {
         if constexpr (std::is_same<CS, __half>::value) {
             return hipErrorInvalidValue;           // FP16 split is built for d = 3
@@ -1364,37 +1399,44 @@ hipError_t launch_apply_batch(const TaskList &tl, int P, int op, Prec prec, int 
 
 template <int P, bool STIFF>
 static hipError_t launch_apply_o(const PatchView &pv, Prec prec, const void *C, const float *rs, const double *x,
-                                 double *y, hipStream_t s, int lz)
+                                 double *y, hipStream_t s, int lz, bool tiled)
 {
-    if (prec == Prec::F64) return launch_apply_t<P, STIFF, double>(pv, (const double *)C, rs, x, y, s, lz);
-    if (prec == Prec::F16S) return launch_apply_t<P, STIFF, __half>(pv, (const __half *)C, rs, x, y, s, lz);
-    return launch_apply_t<P, STIFF, float>(pv, (const float *)C, rs, x, y, s, lz);
+    if (prec == Prec::F64) return launch_apply_t<P, STIFF, double>(pv, (const double *)C, rs, x, y, s, lz, tiled);
+    if (prec == Prec::F16S) return launch_apply_t<P, STIFF, __half>(pv, (const __half *)C, rs, x, y, s, lz, tiled);
+    return launch_apply_t<P, STIFF, float>(pv, (const float *)C, rs, x, y, s, lz, tiled);
 }
 
 template <int P>
 static hipError_t launch_apply_p(const PatchView &pv, int op, Prec prec, const void *C, const float *rs,
-                                 const double *x, double *y, hipStream_t s, int lz)
+                                 const double *x, double *y, hipStream_t s, int lz, bool tiled)
 {
-    return op == 2 ? launch_apply_o<P, true>(pv, prec, C, rs, x, y, s, lz)
-                   : launch_apply_o<P, false>(pv, prec, C, rs, x, y, s, lz);
+    return op == 2 ? launch_apply_o<P, true>(pv, prec, C, rs, x, y, s, lz, tiled)
+                   : launch_apply_o<P, false>(pv, prec, C, rs, x, y, s, lz, tiled);
 }
 
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *C, const double *x, double *y,
-                        hipStream_t s, int lz, const float *rs)
+                        hipStream_t s, int lz, const float *rs, bool tiled)
 {
     hipError_t e = launch_fill(y, pv.N, 0.0, s);
     if (e != hipSuccess) return e;
     switch (pv.P) {
-    case 2: return launch_apply_p<2>(pv, op, prec, C, rs, x, y, s, lz);
-    case 3: return launch_apply_p<3>(pv, op, prec, C, rs, x, y, s, lz);
-    case 4: return launch_apply_p<4>(pv, op, prec, C, rs, x, y, s, lz);
-    case 5: return launch_apply_p<5>(pv, op, prec, C, rs, x, y, s, lz);
-    case 6: return launch_apply_p<6>(pv, op, prec, C, rs, x, y, s, lz);
-    case 7: return launch_apply_p<7>(pv, op, prec, C, rs, x, y, s, lz);
-    case 8: return launch_apply_p<8>(pv, op, prec, C, rs, x, y, s, lz);
-    case 9: return launch_apply_p<9>(pv, op, prec, C, rs, x, y, s, lz);
+    case 2: return launch_apply_p<2>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 3: return launch_apply_p<3>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 4: return launch_apply_p<4>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 5: return launch_apply_p<5>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 6: return launch_apply_p<6>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 7: return launch_apply_p<7>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 8: return launch_apply_p<8>(pv, op, prec, C, rs, x, y, s, lz, tiled);
+    case 9: return launch_apply_p<9>(pv, op, prec, C, rs, x, y, s, lz, tiled);
     default: return hipErrorInvalidValue;
     }
+}
+
+bool apply_tiled_layout(int P, int op, Prec prec)
+{
+    if (P < 2 || P > kMaxOrder || prec == Prec::F16S || prec == Prec::BF16X3) return false;
+    const ApplyShape sh = apply_shape(P, prec == Prec::F64 ? 0 : 1, op == 2);
+    return sh.ROWS != 0 && sh.ALAY != 0;
 }
 
 }  // namespace sfiga

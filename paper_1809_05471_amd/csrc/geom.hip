@@ -50,18 +50,28 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
         o.xyz[qlin * 3 + 1] = G[1];
         o.xyz[qlin * 3 + 2] = G[2];
     }
+    const int P = pv.P, K0 = pv.dir[0].K, Q2 = pv.dir[2].Q;
     if (o.c_mass) {
         double v = wd * eval_coef(o.coef_mass, G, 3, qlin);
         int64_t idx = coef_index(3, 1, 0, q0, q1, q2, Q0, Q1);
         if (f32) store_coef<float>(o.c_mass, idx, v); else store_coef<double>(o.c_mass, idx, v);
+        if (o.ca_mass) {
+            idx = apply_coef_index(1, 0, q0, q1, q2, P, K0, Q2);
+            if (f32) store_coef<float>(o.ca_mass, idx, v); else store_coef<double>(o.ca_mass, idx, v);
+        }
     }
     if (o.c_stiff) {
         double s = wd * eval_coef(o.coef_stiff, G, 3, qlin);
         for (int i = 0; i < 3; ++i)
             for (int j = i; j < 3; ++j) {
                 double v = s * (inv[i][0] * inv[j][0] + inv[i][1] * inv[j][1] + inv[i][2] * inv[j][2]);
-                int64_t idx = coef_index(3, 6, sym_comp<3>(i, j), q0, q1, q2, Q0, Q1);
+                const int c = sym_comp<3>(i, j);
+                int64_t idx = coef_index(3, 6, c, q0, q1, q2, Q0, Q1);
                 if (f32) store_coef<float>(o.c_stiff, idx, v); else store_coef<double>(o.c_stiff, idx, v);
+                if (o.ca_stiff) {
+                    idx = apply_coef_index(6, c, q0, q1, q2, P, K0, Q2);
+                    if (f32) store_coef<float>(o.ca_stiff, idx, v); else store_coef<double>(o.ca_stiff, idx, v);
+                }
             }
     }
 }

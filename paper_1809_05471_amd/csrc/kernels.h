@@ -48,6 +48,30 @@ __host__ __device__ inline int64_t split_size(int ncomp, int P, int K0, int K1, 
     return (int64_t)K2 * P * ncomp * gy * gx * T * T;
 }
 
+// Coefficient layout of the apply's element-row kernel (d = 3), tile by
+// tile: for each tile of T x T quadrature columns (T = apply_tile_elems(P) *
+// P; tiles in directions 1 and 2, direction 1 fastest), each quadrature plane
+// q3 and each pair of components, the tile's columns (row ty, column tx) with
+// the two components of a pair side by side (one component for the mass
+// operator).  A workgroup then reads one contiguous block per layer, two
+// values per load.  Columns outside the patch hold 0.
+__host__ __device__ inline int apply_coef_width(int ncomp) { return ncomp > 1 ? 2 : 1; }
+__host__ __device__ inline int64_t apply_coef_index(int ncomp, int comp, int q0, int q1, int q2, int P, int K0, int Q2)
+{
+    const int T = apply_tile_elems(P) * P, W = apply_coef_width(ncomp);
+    const int gx = (K0 * P + T - 1) / T;
+    const int bx = q0 / T, by = q1 / T;
+    const int64_t tile = (int64_t)by * gx + bx;
+    return (((tile * Q2 + q2) * (ncomp / W) + comp / W) * (T * T) + (int64_t)(q1 - by * T) * T + (q0 - bx * T)) * W +
+           comp % W;
+}
+__host__ __device__ inline int64_t apply_coef_size(int ncomp, int P, int K0, int K1, int K2)
+{
+    const int T = apply_tile_elems(P) * P;
+    const int64_t gx = (K0 * P + T - 1) / T, gy = (K1 * P + T - 1) / T;
+    return gx * gy * (int64_t)K2 * P * ncomp * T * T;
+}
+
 struct PatchView {
     int d, P;
     Dir dir[3];            // unused directions: K = N = Q = 1, tables null
@@ -60,6 +84,8 @@ struct PatchView {
 struct GeomOut {
     void *c_mass;          // [Q] (layout: see coef_index), Prec element type, or null
     void *c_stiff;         // [Q][ncomp], or null
+    void *ca_mass;         // the same in the apply's tiled layout (apply_coef_index, d = 3), or null
+    void *ca_stiff;
     double *xyz;           // [Q][d] physical quadrature points, or null
     Coef coef_mass, coef_stiff;
     int *bad_det;          // device flag set to 1 if det J <= 0 somewhere, or null
@@ -149,8 +175,13 @@ hipError_t launch_gather_cyclic(const PatchView &pv, const PatchView &alt, int s
 // op: 1 mass, 2 stiffness; c: coefficient tensor of that op at prec
 // lz: element layers per workgroup in direction 3 (0 = default)
 // rs: per-element reference and scale of the F16S storage (null otherwise)
+// tiled: c is in the tiled layout of apply_coef_index (only where
+// apply_tiled_layout says the kernel reads it), else in the layout of coef_index
 hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, const double *x, double *y,
-                        hipStream_t s, int lz = 0, const float *rs = nullptr);
+                        hipStream_t s, int lz = 0, const float *rs = nullptr, bool tiled = false);
+// true if the d = 3 apply of op at prec and order P reads its coefficients
+// in the tiled layout (the geometry step then writes that copy as well)
+bool apply_tiled_layout(int P, int op, Prec prec);
 // F16S storage from the FP32 coefficient tensor c32 of op (d = 3): per element
 // and component the reference r = (max + min) / 2 and scale s = (max - min) / 2
 // of C / w over the element's points (rs [K3][K2][K1][ncomp][2]), and per point

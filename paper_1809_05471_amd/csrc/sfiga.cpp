@@ -43,6 +43,11 @@ struct sf_patch {
     // [op][storage: FP64, FP32, FP16 residual of the FP16 split]
     void *C[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     float *rs[2] = {nullptr, nullptr};   // [op] per-element reference and scale of the FP16 split
+    // [op][storage: FP64, FP32] the coefficient tensor in the apply's tiled
+    // layout (d = 3, where the apply kernel of the order reads it), written
+    // by the geometry step beside C
+    void *CA[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool assembly_only = false;          // the relabelled copy of a patch: no apply
     bool ready[2][4] = {};               // [op][precision mode]
     // level-2 workspace of the d = 3 assembly, sized once for the largest
     // (operator, precision) so that captured graphs never see it move
@@ -167,6 +172,8 @@ void free_patch_memory(sf_patch *p)
     (void)hipFree(p->ws);
     (void)hipFree(p->tmpv);
     for (auto &a : p->C)
+        for (void *c : a) (void)hipFree(c);
+    for (auto &a : p->CA)
         for (void *c : a) (void)hipFree(c);
     for (float *r : p->rs) (void)hipFree(r);
 }
@@ -435,12 +442,25 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
         if (st == SF_OK && pi == 3)
             st = alloc(&p->C[oi][2], 2 * (size_t)split_size(ncomp(oi, p->d), p->P, p->view.dir[0].K,
                                                               p->view.dir[1].K, p->view.dir[2].K));
+        const bool tiled = p->d == 3 && !p->assembly_only &&
+                           apply_tiled_layout(p->P, oi + 1, gi == 0 ? Prec::F64 : Prec::F32);
+        if (st == SF_OK && tiled && !p->CA[oi][gi]) {
+            // columns outside the patch are never written: cleared once here
+            const size_t bytes = esz * (size_t)apply_coef_size(ncomp(oi, p->d), p->P, p->view.dir[0].K,
+                                                                 p->view.dir[1].K, p->view.dir[2].K);
+            st = alloc(&p->CA[oi][gi], bytes);
+            if (st == SF_OK) {
+                hipError_t e0 = hipMemsetAsync(p->CA[oi][gi], 0, bytes, s);
+                if (e0 != hipSuccess) st = hip_fail(ctx, e0, "apply coefficient layout");
+            }
+        }
         if (st == SF_OK && pi == 3) st = alloc((void **)&p->rs[oi], sizeof(float) * 2 * ncomp(oi, p->d) * nel);
         if (st != SF_OK) return st;
         // the modes stored in what this call rewrites are stale until it is done
         for (int m = 0; m < 4; ++m)
             if (geom_storage(m) == gi) p->ready[oi][m] = false;
         if (oi == 0) o.c_mass = p->C[oi][gi]; else o.c_stiff = p->C[oi][gi];
+        if (tiled) (oi == 0 ? o.ca_mass : o.ca_stiff) = p->CA[oi][gi];
     }
     hipError_t e = sync ? hipMemsetAsync(p->dflag, 0, sizeof(int), s) : hipSuccess;
     if (e == hipSuccess) e = launch_geometry(p->view, o, s);
@@ -654,6 +674,7 @@ static sf_status make_alt(sf_patch *p, int sh)
     sf_patch *a = nullptr;
     sf_status st = sf_patch_create(ctx, &d, &a);
     if (st != SF_OK) return st;
+    a->assembly_only = true;
     a->coef[0] = p->coef[0];
     a->coef[1] = p->coef[1];
     e = hipMalloc((void **)&p->tmpv, sizeof(double) * (size_t)p->view.nnz);
@@ -795,7 +816,8 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
     if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
     int oi = op == SF_MASS ? 0 : 1;
     const Prec pr = apply_prec(pi);
-    const void *C = p->C[oi][cidx(pi)];
+    const bool tiled = pi != 3 && p->CA[oi][geom_storage(pi)] != nullptr;
+    const void *C = tiled ? p->CA[oi][geom_storage(pi)] : p->C[oi][cidx(pi)];
     hipStream_t s = p->ctx->stream;
     if (p->tune_lz[oi][pi] < 0) {
         // autotuner: element layers per workgroup, timed on this patch into y
@@ -805,7 +827,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             hipEvent_t e0 = nullptr, e1 = nullptr;
             hipError_t e = hipEventCreate(&e0);
             if (e == hipSuccess) e = hipEventCreate(&e1);
-            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, 0, p->rs[oi]);   // warm-up
+            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, 0, p->rs[oi], tiled);   // warm-up
             float best = 1e30f;
             for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
                 if (e != hipSuccess || lz > p->view.dir[2].K) break;
@@ -813,7 +835,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
                     float t = 0.f;
                     e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz, p->rs[oi]);
+                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz, p->rs[oi], tiled);
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -829,7 +851,7 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
         }
     }
-    hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi], p->rs[oi]);
+    hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi], p->rs[oi], tiled);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
     return SF_OK;
 }

@@ -704,6 +704,31 @@ def test_async_prepare_and_geometry_check():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec,tol", [(sf.SF_FP64, TOL64), (sf.SF_FP32, TOL32)])
+def test_apply_follows_a_new_coefficient(prec, tol):
+    """Order 6 (tiled coefficient copy of the apply in FP64, the coef_index
+    layout in FP32): apply, change the stiffness coefficient, prepare again,
+    apply again; both products against the oracle (ragged apply tiles in
+    directions 1 and 2, several layers)."""
+    K, p = (7, 8, 5), 6
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=23)
+    x = None
+    with GpuPatch(kn, p, ctrl, ("sinprod", 0.5)) as g:
+        for alpha in (0.5, -0.7):
+            P = oracle.Problem(kn, p, ctrl, ("sinprod", alpha))
+            if x is None:
+                x = inputs.random_vector(P.N, 5)
+            sf.sf_patch_set_coef(g.ctx, g.h, sf.SF_STIFF, sf.SF_COEF_SINPROD, alpha)
+            g.prepare(sf.SF_MASS | sf.SF_STIFF, prec)
+            for op in (sf.SF_STIFF, sf.SF_MASS):
+                rp_o, ci_o, v_o = P.assemble(op)
+                absAx = np.zeros(P.N)
+                np.add.at(absAx, np.repeat(np.arange(P.N), np.diff(rp_o)), np.abs(v_o) * np.abs(x[ci_o]))
+                ey = err_y(g.apply(op, x, prec), P.apply(op, x), absAx)
+                record("err_y", prec, ey)
+                assert ey <= tol, (alpha, op, ey)
+
+
 def test_quad_points_leave_the_det_flag_alone():
     """sf_patch_quad_points evaluates G only: on a folded map it does not
     record a det J failure, so the next sf_patch_geometry_check (which reports
