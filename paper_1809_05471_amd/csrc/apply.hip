@@ -33,38 +33,39 @@ struct STile {
 
 // Per (order, operator, storage type) shape of the d = 3 kernel, chosen by
 // measurement (stiffness, N = 126^3, and 128^3 at order 6):
+//   ROWS   the element-row form (apply3d_rows_block): the stiffness apply at
+//          every order in FP64, and from order 3 in FP32 and FP16 split
+//          (N = 126^3, ms FP64 / FP32 before -> after: order 4 1.55 -> 1.23 /
+//          0.94 -> 0.70, order 6 6.58 -> 4.98 / 4.18 -> 2.90, order 8 38.9
+//          -> 23.2 / 10.8 -> 7.3, order 9 42.7 -> 28.1 / 20.3 -> 16.9); the
+//          mass apply and order 2 in FP32 keep apply3d_block;
+//   ALAY   with ROWS, the coefficients in the tiled copy (apply_coef_index);
 //   G      the layer's p quadrature planes go through the plane stages
-//          (forward 2 and 1, pointwise, backward 1 and 2) in G groups of
-//          ceil(p / G) planes: less LDS per workgroup, but more barriers and
-//          less cover for the coefficient loads (it pays only for FP64 at
-//          order 8);
-//   CMODE  how the coefficients reach the pointwise stage: 0 plane by plane
-//          in that stage; 1 the group's planes loaded at the start of the
-//          group (the first group's at the start of the layer, before the
-//          forward direction-3 stage); 2 the next group's planes (the next layer's first group
-//          after the last) loaded right after the pointwise stage, so that
-//          they have the backward stages to arrive;
-//   TWOSTEP backward directions 1 and 2 in two steps (per-element sums in
-//          place, then sums over the elements sharing a function);
-//   UNRJ   the output loop of those per-element sums unrolled: more
-//          independent work per item, but the compiler then holds all p^2
-//          table values of an element in registers (FP64 at order 6: 188
-//          instead of 120 VGPRs, one workgroup per CU instead of two);
-//   XCD    tiles dealt to the XCDs in contiguous ranges (xcd_tile): a tile row
-//          of coefficients is TX values, not a whole number of 128-byte
-//          lines, so neighbouring tiles share the lines at their ends; on one
-//          XCD those are fetched once (128^3 order 6 FP64: 39 -> 27 GB
-//          fetched per apply).  It pays where the kernel waits on HBM (low
-//          orders); from order 5 on the kernel waits on LDS and barriers and
-//          the remap costs 2-6%.
-//   JU, FU with UNRJ = 0, the unroll counts of that loop and of the field loop
-//          of backward direction 1 (two output chains at a time: FP64 order 6
-//          7.94 -> 7.60 ms at 128^3, order 9 46.3 -> 42.7 ms at 118^3);
-//   W      minimum resident waves per SIMD asked of the compiler (register cap).
-// Measured at 128^3 order 6 FP64 (ms per apply): 12.43 before the x-row and
-// table prefetch and the parallel backward direction 3, 11.06 after, 7.95
-// with UNRJ = 0; the coefficients of the whole layer in registers (CMODE 1)
-// cost the second workgroup per CU there (16.6).
+//          in G groups of ceil(p / G) planes: less LDS per workgroup (a
+//          second workgroup per CU at orders 8 and 9), but more barriers;
+//   CMODE  how the coefficients reach the pointwise stage: 0 loaded in that
+//          stage; 1 the layer's (apply3d_block: the group's) planes loaded at
+//          the start of the layer; 2 the next layer's (apply3d_block: the next
+//          group's) planes loaded from the pointwise stage on, so that they
+//          have the backward stages to arrive;
+//   TWOSTEP (apply3d_block) backward directions 1 and 2 in two steps
+//          (per-element sums in place, then sums over the elements sharing a
+//          function);
+//   UNRJ   (apply3d_block) the output loop of those per-element sums
+//          unrolled: more independent work per item, but the compiler then
+//          holds all p^2 table values of an element in registers;
+//   XCD    tiles dealt to the XCDs in contiguous ranges (xcd_tile): a tile
+//          row of row-layout coefficients is TX values, not a whole number of
+//          128-byte lines, so neighbouring tiles share the lines at their
+//          ends; on one XCD those are fetched once;
+//   JU, FU (apply3d_block, UNRJ = 0) the unroll counts of that loop and of the
+//          field loop of backward direction 1;
+//   W      minimum resident waves per SIMD asked of the compiler (register
+//          cap).  A workgroup of six waves spreads 2, 2, 1, 1 over the four
+//          SIMDs, so two of them per CU need four waves per SIMD: 128 VGPRs.
+// Measured at 128^3 order 6 FP64 (ms per apply): 12.43 in the first
+// apply3d_block, 7.57 in its last form, 6.68 in the element-row form on the
+// row layout and 5.54 on the tiled copy.
 struct ApplyShape {
     int G, CMODE, TWOSTEP, UNRJ, W, XCD;
     int JU = 1;            // with UNRJ = 0: unroll count of the per-element output loops
@@ -78,17 +79,16 @@ constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
 {
     const bool f64 = storage == 0;
     // BEGIN SHAPES
-    if (!stiff || P == 2) return ApplyShape{1, 2, f64 ? P >= 3 : P >= 5, 1, 1, P == 2 || (!f64 && P <= 4)};
-    if (f64) {
-        if (P <= 4) return ApplyShape{1, P == 4 ? 1 : 0, 1, 1, 1, 0};
-        if (P == 8) return ApplyShape{8, 1, 1, 0, 1, 0};
-        if (P == 5) return ApplyShape{1, 0, 1, 0, 1, 0, 2, 3};
-        if (P == 7) return ApplyShape{1, 0, 1, 0, 1, 0, 1, 3};
-        if (P == 6) return ApplyShape{1, 2, 1, 0, 4, 1, 1, 1, 1, 1};
-        return ApplyShape{1, 0, 1, 0, 1, 0, 2, 1};
+    // element-row form with the tiled coefficient copy (FP64, FP32) or the
+    // FP16-split storage; coefficients a layer ahead (CMODE 2), or plane
+    // groups with their own loads where one workgroup per CU would be left
+    if (stiff && (f64 || P > 2)) {
+        const int alay = storage == 2 ? 0 : 1;
+        if (P == 8 && storage != 2) return ApplyShape{2, 0, 1, 0, 4, 1, 1, 1, 1, alay};
+        if (P == 9 && storage == 1) return ApplyShape{3, 0, 1, 0, 4, 1, 1, 1, 1, alay};
+        return ApplyShape{1, 2, 1, 0, P <= 6 ? 4 : 2, 1, 1, 1, 1, alay};
     }
-    if (storage == 2) return ApplyShape{1, P == 2 ? 2 : (P == 8 ? 1 : 0), P >= 5, 1, 1, P <= 4};
-    if (P == 4) return ApplyShape{1, 0, 0, 1, 1, 1};
+    if (!stiff || P == 2) return ApplyShape{1, 2, f64 ? P >= 3 : P >= 5, 1, 1, P == 2 || (!f64 && P <= 4)};
     return ApplyShape{1, 1, P >= 5, 1, 1, P <= 4};
     // END SHAPES
 }
@@ -675,7 +675,7 @@ constexpr int rows_lds_elems()
 //   B2  the same in direction 2 (element row l2), then the sums
 //   B3  the transposed direction-3 sums into the y window (function column,
 //       group of rows)
-template <int P, bool STIFF, typename CS, bool ALAY>
+template <int P, bool STIFF, typename CS, bool ALAY, int CM>
 __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS *__restrict__ C,
                                                    const float *__restrict__ rs, const double *__restrict__ x,
                                                    double *__restrict__ y, int LZ, int bx, int by, int bz)
@@ -697,7 +697,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     constexpr int SHF = PG * TY * HS;      // one field of the point values of a group
     constexpr int SBF = PG * TY * BS;      // one field of the direction-2 values of a group
     constexpr int SA = NA * P * AS, SH = NF * SHF;
-    static_assert(G == 1 || CF::CMODE == 0, "plane groups load their coefficients in the pointwise stage");
+    static_assert(G == 1 || CM == 0, "plane groups load their coefficients in the pointwise stage");
     // LDS: x and y windows [P slots][NY][NX]; ra the forward direction-3
     // results sa and then the backward direction-2 sums sq, [NA][P][AS]; rh
     // the point values sh [NF][PG][TY][HS]; rb the forward direction-2
@@ -821,9 +821,9 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     // the coefficient loads are spread over three stages (planes [0, p/3) at
     // the end of the pointwise stage, then the rest after backward stages 1
     // and 2) so that their issue does not stall one stage.
-    constexpr bool T3L = CF::CMODE == 2;
+    constexpr bool T3L = CM == 2;
     double xn, tnW, tnB = 0.0, tnD = 0.0;
-    CS cur[CF::CMODE ? P : PG][NC];
+    CS cur[CM ? P : PG][NC];
     auto load_layer_head = [&](int e3) {
         const int tid = thread_index();
         const int xlx = tid % NX, xly = tid / NX;
@@ -840,7 +840,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
         }
     };
     auto load_planes = [&](int e3, int lo, int hi) {
-        if constexpr (CF::CMODE != 0) {
+        if constexpr (CM != 0) {
             const int e3c = e3 <= e3z ? e3 : e3z;
             const Col c = column();
 #pragma unroll
@@ -857,7 +857,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             }
         }
     };
-    if constexpr (CF::CMODE == 2) {
+    if constexpr (CM == 2) {
         load_layer_head(e3a);
         store_t3(e3a);
         load_planes(e3a, 0, P);
@@ -867,7 +867,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     for (int e3 = e3a; e3 <= e3z; ++e3) {
         const bool more = e3 < e3z;
         const CT *t3W = t3Wb + (e3 & 1) * P;
-        if constexpr (CF::CMODE != 2) {
+        if constexpr (CM != 2) {
             load_layer_head(e3);
             load_planes(e3, 0, P);
         }
@@ -975,7 +975,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             // ---- PW: the pointwise coefficient, one thread per quadrature column, in place
             {
                 const Col c = column();
-                if constexpr (CF::CMODE == 0) {
+                if constexpr (CM == 0) {
 #pragma unroll
                     for (int gl = 0; gl < PG; ++gl) load_plane(c, e3, g0 + gl < P ? g0 + gl : P - 1, cur[gl]);
                 }
@@ -995,7 +995,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
 #pragma unroll
                     for (int gl = 0; gl < PG; ++gl) {
                         if (gl >= npl) break;
-                        const CS *cr = cur[CF::CMODE ? (G == 1 ? gl : 0) : gl];
+                        const CS *cr = cur[CM ? (G == 1 ? gl : 0) : gl];
                         CT cg[NC];
 #pragma unroll
                         for (int k = 0; k < NC; ++k) {
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                     }
                 }
             }
-            if constexpr (CF::CMODE == 2) {
+            if constexpr (CM == 2) {
                 load_layer_head(e3 + 1);
                 load_planes(e3 + 1, 0, P / 3);
             }
@@ -1053,7 +1053,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                     }
                 }
             }
-            if constexpr (CF::CMODE == 2) load_planes(e3 + 1, P / 3, 2 * P / 3);
+            if constexpr (CM == 2) load_planes(e3 + 1, P / 3, 2 * P / 3);
             __syncthreads();
             // then per function column lx the sum over the <= p elements that share it
             for (int idx = thread_index(); idx < npl * TY * NX; idx += NT) {
@@ -1118,7 +1118,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                     }
                 }
             }
-            if constexpr (CF::CMODE == 2) load_planes(e3 + 1, 2 * P / 3, P);
+            if constexpr (CM == 2) load_planes(e3 + 1, 2 * P / 3, P);
             __syncthreads();
             // then per function row the sum over the <= p elements that share it, into sq
             for (int idx = thread_index(); idx < npl * NXY; idx += NT) {
@@ -1193,7 +1193,7 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     if (ApplyCfgS<P, STIFF, CS>::XCD) xcd_tile(bx, by, bz);
     if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
-        apply3d_rows_block<P, STIFF, CS, ALAY>(pv, C, rs, x, y, LZ, bx, by, bz);
+        apply3d_rows_block<P, STIFF, CS, ALAY, ApplyCfgS<P, STIFF, CS>::CMODE>(pv, C, rs, x, y, LZ, bx, by, bz);
     else
         apply3d_block<P, STIFF, CS>(pv, C, rs, x, y, LZ, bx, by, bz);
 }
@@ -1209,8 +1209,10 @@ __global__ __launch_bounds__(STile<P>::NT, (ApplyCfgS<P, STIFF, CS>::W)) void ap
         const int bx = (int)(l % T.gx);
         const int64_t r = l / T.gx;
         if constexpr (ApplyCfgS<P, STIFF, CS>::ROWS)
-            apply3d_rows_block<P, STIFF, CS, false>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx,
-                                                    (int)(r % T.gy), (int)(r / T.gy));
+            // the coefficients in the pointwise stage: the persistent loop
+            // leaves no registers for a layer of them in flight
+            apply3d_rows_block<P, STIFF, CS, false, 0>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx,
+                                                       (int)(r % T.gy), (int)(r / T.gy));
         else
             apply3d_block<P, STIFF, CS>(T.pv, (const CS *)T.C, T.rs, T.x, T.out, T.arg, bx, (int)(r % T.gy),
                                         (int)(r / T.gy));
