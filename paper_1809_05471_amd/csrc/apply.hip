@@ -1055,41 +1055,73 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             }
             if constexpr (CM == 2) load_planes(e3 + 1, P / 3, 2 * P / 3);
             __syncthreads();
-            // then per function column lx the sum over the <= p elements that share it
-            for (int idx = thread_index(); idx < npl * TY * NX; idx += NT) {
-                const int lx = idx % NX, rr = idx / NX;          // rr = gl * TY + yy
-                CT rv[NF];
+            // With more elements per tile than points per element (orders 2
+            // and 3), the sums over the elements that share a function column
+            // get a stage of their own (into rb); otherwise backward direction
+            // 2 forms them as it reads its inputs.
+            constexpr bool FOLD1 = E <= P;
+            if constexpr (!FOLD1) {
+                for (int idx = thread_index(); idx < npl * TY * NX; idx += NT) {
+                    const int lx = idx % NX, rr = idx / NX;          // rr = gl * TY + yy
+                    CT rv[NF];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) rv[f] = CT(0);
+                    for (int f = 0; f < NF; ++f) rv[f] = CT(0);
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const int l1 = lx - j;                       // element whose local function j is lx
-                    if (l1 < 0 || l1 >= E) continue;
+                    for (int j = 0; j < P; ++j) {
+                        const int l1 = lx - j;                       // element whose local function j is lx
+                        if (l1 < 0 || l1 >= E) continue;
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) rv[f] += rh[f * SHF + rr * HS + l1 * P + j];
+                        for (int f = 0; f < NF; ++f) rv[f] += rh[f * SHF + rr * HS + l1 * P + j];
+                    }
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) rb[f * SBF + rr * BS + lx] = rv[f];
                 }
-#pragma unroll
-                for (int f = 0; f < NF; ++f) rb[f * SBF + rr * BS + lx] = rv[f];
+                __syncthreads();
             }
-            __syncthreads();
             // ---- B2, per element row l2 and (plane, function column): the p
-            // transposed sums over the element's points, written over the
-            // element's own rows: the B-part from fields 0 and 1 into field 0,
-            // then the D-part from field 2 into field 1 (each field is read
-            // before it is overwritten)
+            // transposed sums over the element's points of the backward
+            // direction-1 results, into the element's own rows of rb (the
+            // B-part from fields 0 and 1 into field 0, the D-part from field 2
+            // into field 1; each field is read before it is overwritten).
+            // With FOLD1 each input, the direction-1 sum at function column lx,
+            // is formed here from the per-element parts of the <= p elements
+            // that share lx.
             for (int idx = thread_index(); idx < E * RM::R2; idx += NT) {
                 const int l2 = idx / RM::R2, r = idx % RM::R2;
                 const uniform_ptr<CT> T2B = elem_table(B2g, e2b + l2, d1.K, PP);
                 const uniform_ptr<CT> T2D = elem_table(D2g, e2b + l2, d1.K, PP);
                 if (r < npl * NX) {
                     const int gl = r / NX, lx = r % NX;
-                    CT *o = rb + (gl * TY + l2 * P) * BS + lx;   // point h: o[h BS]
+                    const CT *hrow = rh + (gl * TY + l2 * P) * HS;   // point row hh: hrow[hh HS]
+                    auto sum1 = [&](int f, int hh) -> CT {
+                        if constexpr (!FOLD1) return rb[f * SBF + (gl * TY + l2 * P + hh) * BS + lx];
+                        CT v = CT(0);
+                        if constexpr (E <= P) {
+#pragma unroll
+                            for (int l1 = 0; l1 < E; ++l1) {
+                                const int j = lx - l1;
+                                const bool ok = j >= 0 && j < P;
+                                const CT t = hrow[f * SHF + hh * HS + l1 * P + (ok ? j : 0)];
+                                v += ok ? t : CT(0);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < P; ++j) {
+                                const int l1 = lx - j;
+                                const bool ok = l1 >= 0 && l1 < E;
+                                const CT t = hrow[f * SHF + hh * HS + (ok ? l1 : 0) * P + j];
+                                v += ok ? t : CT(0);
+                            }
+                        }
+                        return v;
+                    };
+                    CT *o = rb + (gl * TY + l2 * P) * BS + lx;   // output function row j: o[j BS]
                     {
                         CT v0[P], v1[P], pB[P];
 #pragma unroll
                         for (int hh = 0; hh < P; ++hh) {
-                            v0[hh] = o[hh * BS];
-                            if (STIFF) v1[hh] = o[SBF + hh * BS];
+                            v0[hh] = sum1(0, hh);
+                            if (STIFF) v1[hh] = sum1(1, hh);
                             pB[hh] = CT(0);
                         }
 #pragma unroll
@@ -1106,7 +1138,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                         CT v[P], pD[P];
 #pragma unroll
                         for (int hh = 0; hh < P; ++hh) {
-                            v[hh] = o[2 * SBF + hh * BS];
+                            v[hh] = sum1(2, hh);
                             pD[hh] = CT(0);
                         }
 #pragma unroll
