@@ -710,6 +710,18 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     CT *rh = yw + P * NXY;
     CT *ra = G == 1 ? rh : rh + SH;
     CT *rb = rh + (G == 1 ? (SA > SH ? SA : SH) : SA + SH);
+    // FOLD1 (elements per tile <= p): backward direction 2 forms the sums
+    // over the elements that share a function column as it reads its inputs.
+    // ATOM2 (FOLD1 in FP64): it also adds its results straight into the
+    // direction-2 sums sq with LDS atomics (the <= p elements that share a
+    // function row meet there); sq then lies in rb with one plane group (rb is
+    // free from the pointwise stage on) and in ra with several.  The FP32 LDS
+    // atomics measured slower than the separate sum (order 6: 4.03 against
+    // 2.63 ms at N = 126^3).
+    constexpr bool FOLD1 = E <= P;
+    constexpr bool ATOM2 = FOLD1 && sizeof(CT) == sizeof(double);
+    static_assert(!(ATOM2 && G == 1) || NA * P * AS <= NF * SBF, "sq fits in rb");
+    CT *sq = (ATOM2 && G == 1) ? rb : ra;
     CT *t3Wb = rb + NF * SBF;              // direction-3 weights, [layer parity][g] (FP16 split)
     CT *t3s = t3Wb + 2 * P;                // direction-3 tables with CMODE 2, [layer parity][B, D][g][j]
     static_assert(NXY <= NT, "one prefetched x value per thread");
@@ -911,6 +923,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
         for (int grp = 0; grp < G; ++grp) {
             const int g0 = grp * PG;
             const int npl = P - g0 < PG ? P - g0 : PG;          // planes in this group
+
             // ---- F2: per element row l2 and (plane, function column): B2 a, D2 a, B2 b at its p points
             for (int idx = thread_index(); idx < E * RM::R2; idx += NT) {
                 const int l2 = idx / RM::R2, r = idx % RM::R2;
@@ -948,6 +961,14 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             // ---- F1, per element l1 and (plane, point row): the gradient (mass:
             // the value) at the element's p points from the p function values of
             // each field, into sh
+            if constexpr (ATOM2 && G > 1) {
+                // this group's planes of sq (in ra; their sa values are dead
+                // now) start from zero: backward direction 2 adds into them
+                for (int i = thread_index(); i < NA * npl * AS; i += NT) {
+                    const int k = i / (npl * AS), rem = i % (npl * AS);
+                    sq[(k * P + g0) * AS + rem] = CT(0);
+                }
+            }
             for (int idx = thread_index(); idx < E * RM::R1; idx += NT) {
                 const int l1 = idx / RM::R1, r = idx % RM::R1;
                 const uniform_ptr<CT> T1B = elem_table(B1g, e1b + l1, d0.K, PP);
@@ -973,6 +994,10 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             }
             __syncthreads();
             // ---- PW: the pointwise coefficient, one thread per quadrature column, in place
+            if constexpr (ATOM2 && G == 1) {
+                // sq (in rb, whose forward direction-2 values are dead) starts from zero
+                for (int i = thread_index(); i < NA * P * AS; i += NT) sq[i] = CT(0);
+            }
             {
                 const Col c = column();
                 if constexpr (CM == 0) {
@@ -1059,7 +1084,6 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             // and 3), the sums over the elements that share a function column
             // get a stage of their own (into rb); otherwise backward direction
             // 2 forms them as it reads its inputs.
-            constexpr bool FOLD1 = E <= P;
             if constexpr (!FOLD1) {
                 for (int idx = thread_index(); idx < npl * TY * NX; idx += NT) {
                     const int lx = idx % NX, rr = idx / NX;          // rr = gl * TY + yy
@@ -1116,6 +1140,8 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                         return v;
                     };
                     CT *o = rb + (gl * TY + l2 * P) * BS + lx;   // output function row j: o[j BS]
+                    // ATOM2: function row l2 + j of sq
+                    CT *qo = sq + (g0 + gl) * AS + l2 * NX + lx;
                     {
                         CT v0[P], v1[P], pB[P];
 #pragma unroll
@@ -1132,7 +1158,10 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                                 if (STIFF) pB[j] += T2D[hh * P + j] * v1[hh];
                             }
 #pragma unroll
-                        for (int j = 0; j < P; ++j) o[j * BS] = pB[j];
+                        for (int j = 0; j < P; ++j) {
+                            if constexpr (ATOM2) atomicAdd(qo + j * NX, pB[j]);
+                            else o[j * BS] = pB[j];
+                        }
                     }
                     if constexpr (STIFF) {
                         CT v[P], pD[P];
@@ -1146,13 +1175,18 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
 #pragma unroll
                             for (int j = 0; j < P; ++j) pD[j] += T2B[hh * P + j] * v[hh];
 #pragma unroll
-                        for (int j = 0; j < P; ++j) o[SBF + j * BS] = pD[j];
+                        for (int j = 0; j < P; ++j) {
+                            if constexpr (ATOM2) atomicAdd(qo + P * AS + j * NX, pD[j]);
+                            else o[SBF + j * BS] = pD[j];
+                        }
                     }
                 }
             }
             if constexpr (CM == 2) load_planes(e3 + 1, 2 * P / 3, P);
             __syncthreads();
-            // then per function row the sum over the <= p elements that share it, into sq
+            // then (without ATOM2) per function row the sum over the <= p
+            // elements that share it, into sq
+            if constexpr (!ATOM2) {
             for (int idx = thread_index(); idx < npl * NXY; idx += NT) {
                 const int j2 = idx % NXY, gl = idx / NXY;
                 const int lx = j2 % NX, ly = j2 / NX;
@@ -1165,10 +1199,11 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                     sB += rb[row];
                     if (STIFF) sD += rb[SBF + row];
                 }
-                ra[(g0 + gl) * AS + j2] = sB;
-                if (STIFF) ra[(P + g0 + gl) * AS + j2] = sD;
+                sq[(g0 + gl) * AS + j2] = sB;
+                if (STIFF) sq[(P + g0 + gl) * AS + j2] = sD;
             }
             __syncthreads();
+            }
         }
         // ---- B3: per function column and group of rows s3, into the y window
         for (int idx = thread_index(); idx < RM::GS * RM::RXY; idx += NT) {
@@ -1177,8 +1212,8 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                 CT q[NA][P];
 #pragma unroll
                 for (int g3 = 0; g3 < P; ++g3) {
-                    q[0][g3] = ra[g3 * AS + j];
-                    if (STIFF) q[NA - 1][g3] = ra[(P + g3) * AS + j];
+                    q[0][g3] = sq[g3 * AS + j];
+                    if (STIFF) q[NA - 1][g3] = sq[(P + g3) * AS + j];
                 }
                 CT acc[RM::PG3];
 #pragma unroll
