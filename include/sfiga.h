@@ -218,8 +218,9 @@ sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col
  * precision) times a few tile shapes on this patch (writing into the output,
  * then overwriting it) and synchronizes once.  For d = 3 the first call also
  * allocates the patch's level-2 workspace (the partial sums after the second
- * level of Algorithm 1; at most SFIGA_WORKSPACE_MB MiB, default 4096; larger
- * patches run in chunks of element layers); it is freed by
+ * level of Algorithm 1; at most SFIGA_WORKSPACE_MB MiB if that is set, else
+ * a quarter of the free device memory, at most 32 GiB; larger patches run in
+ * chunks of element layers); it is freed by
  * sf_patch_destroy.  Returns SF_ENOMEM if that allocation fails. */
 sf_status sf_assemble(sf_patch *patch, unsigned ops, sf_precision prec,
                       double *dev_val_mass, double *dev_val_stiff);
