@@ -206,6 +206,12 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     // x2 points per level-1 lane (a divisor of p, bounded by registers)
     constexpr int G2B = (P == 2 || P == 6 || P == 8 || (P == 4 && sizeof(CT) == sizeof(float))) ? 2 : 1;
     constexpr int NGB = P / G2B;
+    // unroll counts of the x1-point loop of level 1 and the x2-point loop of
+    // level 2 on the vector ALU: two iterations in flight hide one LDS
+    // latency each (order 6, 128^3 elements: FP64 79.7 -> 72.3 ms, FP32 level
+    // 2 only 72.1 -> 70.0 ms); elsewhere the registers cost more than that
+    constexpr int U1 = (P == 6 && sizeof(CT) == sizeof(double)) ? 2 : 1;
+    constexpr int U2 = P == 6 ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *cs = reinterpret_cast<CT *>(smem_raw);          // [NCOMP][g2][g1][XE]
     CT *l1 = cs + S::NSLICE;                            // [g2][pair][T1][W]
@@ -365,7 +371,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int e1 = m1 - r;
                 if (e1 < 0 || e1 >= K1) continue;
                 const int le1 = lm1 + P - 1 - r;
-#pragma unroll 1
+#pragma unroll (U1)
                 for (int g1 = 0; g1 < P; ++g1) {
                     const CT av = (CT)ta[(g1 * P + r) * XE + le1];
                     CT bv[P];
@@ -531,7 +537,7 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
                 const int lm1 = it / NH;
                 int c1, c2;
                 half_window<P>(it % NH, c1, c2);
-#pragma unroll 1
+#pragma unroll (U2)
                 for (int g2 = 0; g2 < P; ++g2) {
                     CT L[NP];
 #pragma unroll
