@@ -42,7 +42,8 @@ struct STile {
 //   ALAY   with ROWS, the coefficients in the tiled copy (apply_coef_index);
 //   G      the layer's p quadrature planes go through the plane stages
 //          in G groups of ceil(p / G) planes: less LDS per workgroup (a
-//          second workgroup per CU at orders 8 and 9), but more barriers;
+//          second workgroup per CU at orders 8 and 9), but more barriers
+//          (FP64 order 8, N = 126^3: 19.1 ms with 2 groups, 16.6 with 3);
 //   CMODE  how the coefficients reach the pointwise stage: 0 loaded in that
 //          stage; 1 the layer's (apply3d_block: the group's) planes loaded at
 //          the start of the layer; 2 the next layer's (apply3d_block: the next
@@ -84,7 +85,8 @@ constexpr ApplyShape apply_shape(int P, int storage, bool stiff)
     // groups with their own loads where one workgroup per CU would be left
     if (stiff && (f64 || P > 2)) {
         const int alay = storage == 2 ? 0 : 1;
-        if (P == 8 && storage != 2) return ApplyShape{2, 0, 1, 0, 4, 1, 1, 1, 1, alay};
+        if (P == 8 && f64) return ApplyShape{3, 0, 1, 0, 4, 1, 1, 1, 1, alay};
+        if (P == 8 && storage == 1) return ApplyShape{2, 0, 1, 0, 4, 1, 1, 1, 1, alay};
         if (P == 9 && storage == 1) return ApplyShape{3, 0, 1, 0, 4, 1, 1, 1, 1, alay};
         return ApplyShape{1, 2, 1, 0, P <= 6 ? 4 : 2, 1, 1, 1, 1, alay};
     }
