@@ -722,6 +722,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     // 2.63 ms at N = 126^3).
     constexpr bool FOLD1 = E <= P;
     constexpr bool ATOM2 = FOLD1 && sizeof(CT) == sizeof(double);
+    constexpr int NQ2 = STIFF ? 3 : 1;     // output fields of forward direction 2 (one item each)
     static_assert(!(ATOM2 && G == 1) || NA * P * AS <= NF * SBF, "sq fits in rb");
     CT *sq = (ATOM2 && G == 1) ? rb : ra;
     CT *t3Wb = rb + NF * SBF;              // direction-3 weights, [layer parity][g] (FP16 split)
@@ -926,36 +927,28 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             const int g0 = grp * PG;
             const int npl = P - g0 < PG ? P - g0 : PG;          // planes in this group
 
-            // ---- F2: per element row l2 and (plane, function column): B2 a, D2 a, B2 b at its p points
-            for (int idx = thread_index(); idx < E * RM::R2; idx += NT) {
-                const int l2 = idx / RM::R2, r = idx % RM::R2;
-                const uniform_ptr<CT> T2B = elem_table(B2g, e2b + l2, d1.K, PP);
-                const uniform_ptr<CT> T2D = elem_table(D2g, e2b + l2, d1.K, PP);
+            // ---- F2: per element row l2, output field q and (plane, function
+            // column): B2 a (q = 0), D2 a (q = 1) or B2 b (q = 2) at the
+            // element's p points.  (l2, q) is the same across a wavefront, so
+            // the table of the item is uniform, and the three fields of the
+            // stiffness run on three times the lanes.
+            for (int idx = thread_index(); idx < E * NQ2 * RM::R2; idx += NT) {
+                const int w = __builtin_amdgcn_readfirstlane(idx / RM::R2), r = idx % RM::R2;
+                const int l2 = w / NQ2, q = w % NQ2;
+                const uniform_ptr<CT> T2 = elem_table(q == 1 ? D2g : B2g, e2b + l2, d1.K, PP);
                 if (r < npl * NX) {
                     const int gl = r / NX, lx = r % NX;
-                    CT a[P], b[P];
+                    const CT *in = ra + ((q == 2 ? P : 0) + g0 + gl) * AS + l2 * NX + lx;
+                    CT a[P];
 #pragma unroll
-                    for (int s = 0; s < P; ++s) {
-                        a[s] = ra[(g0 + gl) * AS + (l2 + s) * NX + lx];
-                        if (STIFF) b[s] = ra[(P + g0 + gl) * AS + (l2 + s) * NX + lx];
-                    }
-                    CT *o = rb + (gl * TY + l2 * P) * BS + lx;
+                    for (int s2 = 0; s2 < P; ++s2) a[s2] = in[s2 * NX];
+                    CT *o = rb + q * SBF + (gl * TY + l2 * P) * BS + lx;
 #pragma unroll
                     for (int h2 = 0; h2 < P; ++h2) {
-                        CT vb = CT(0), vd = CT(0), wb = CT(0);
+                        CT v = CT(0);
 #pragma unroll
-                        for (int s = 0; s < P; ++s) {
-                            vb += T2B[h2 * P + s] * a[s];
-                            if (STIFF) {
-                                vd += T2D[h2 * P + s] * a[s];
-                                wb += T2B[h2 * P + s] * b[s];
-                            }
-                        }
-                        o[h2 * BS] = vb;
-                        if (STIFF) {
-                            o[SBF + h2 * BS] = vd;
-                            o[2 * SBF + h2 * BS] = wb;
-                        }
+                        for (int s2 = 0; s2 < P; ++s2) v += T2[h2 * P + s2] * a[s2];
+                        o[h2 * BS] = v;
                     }
                 }
             }
@@ -1104,6 +1097,45 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                 }
                 __syncthreads();
             }
+            // ---- B2 with ATOM2: per element row l2, input field q and (plane,
+            // function column), the p transposed sums over the element's points
+            // of field q's direction-1 sums (formed from the per-element parts
+            // of the <= p elements that share the column), added into the
+            // direction-2 sums sq: B-part from fields 0 (B table) and 1 (D
+            // table), D-part from field 2 (B table).  (l2, q) is the same
+            // across a wavefront.
+            if constexpr (ATOM2) {
+            for (int idx = thread_index(); idx < E * NQ2 * RM::R2; idx += NT) {
+                const int w = __builtin_amdgcn_readfirstlane(idx / RM::R2), r = idx % RM::R2;
+                const int l2 = w / NQ2, q = w % NQ2;
+                const uniform_ptr<CT> T2 = elem_table(q == 1 ? D2g : B2g, e2b + l2, d1.K, PP);
+                if (r < npl * NX) {
+                    const int gl = r / NX, lx = r % NX;
+                    const CT *hrow = rh + q * SHF + (gl * TY + l2 * P) * HS;   // point row hh: hrow[hh HS]
+                    CT v[P], pt[P];
+#pragma unroll
+                    for (int hh = 0; hh < P; ++hh) {
+                        CT acc = CT(0);
+#pragma unroll
+                        for (int l1 = 0; l1 < E; ++l1) {
+                            const int j = lx - l1;
+                            const bool ok = j >= 0 && j < P;
+                            const CT t = hrow[hh * HS + l1 * P + (ok ? j : 0)];
+                            acc += ok ? t : CT(0);
+                        }
+                        v[hh] = acc;
+                        pt[hh] = CT(0);
+                    }
+#pragma unroll
+                    for (int hh = 0; hh < P; ++hh)
+#pragma unroll
+                        for (int j = 0; j < P; ++j) pt[j] += T2[hh * P + j] * v[hh];
+                    CT *qo = sq + ((q == 2 ? P : 0) + g0 + gl) * AS + l2 * NX + lx;   // function row l2 + j
+#pragma unroll
+                    for (int j = 0; j < P; ++j) atomicAdd(qo + j * NX, pt[j]);
+                }
+            }
+            } else {
             // ---- B2, per element row l2 and (plane, function column): the p
             // transposed sums over the element's points of the backward
             // direction-1 results, into the element's own rows of rb (the
@@ -1183,6 +1215,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                         }
                     }
                 }
+            }
             }
             if constexpr (CM == 2) load_planes(e3 + 1, 2 * P / 3, P);
             __syncthreads();
