@@ -669,12 +669,17 @@ constexpr int rows_lds_elems()
 // registers, instead of reading a value and a table entry from LDS for every
 // multiply-add.  Stages per layer (F2 to B2 for each group of PG planes):
 //   F3  a = B3 x, b = D3 x (function column, group of planes)
-//   F2  B2 a, D2 a, B2 b (element row l2: plane, function column)
+//   F2  B2 a, D2 a, B2 b (element row l2 and output field: plane, function
+//       column)
 //   F1  gradients (element l1: plane, point row)
 //   PW  pointwise product with C (one thread per quadrature column)
-//   B1  per-element transposed sums over an element's points (element l1),
-//       then the sums over the elements that share a function
-//   B2  the same in direction 2 (element row l2), then the sums
+//   B1  per-element transposed sums over an element's points (element l1)
+//   B2  the same in direction 2 (element row l2), each input formed from the
+//       per-element parts of the elements that share its function column;
+//       in FP64 the results go into the direction-2 sums with LDS atomics,
+//       otherwise the sums over the elements that share a function row get a
+//       stage of their own (orders 2 and 3 also sum the direction-1 parts in
+//       a stage of their own)
 //   B3  the transposed direction-3 sums into the y window (function column,
 //       group of rows)
 template <int P, bool STIFF, typename CS, bool ALAY, int CM>
@@ -703,9 +708,10 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     // LDS: x and y windows [P slots][NY][NX]; ra the forward direction-3
     // results sa and then the backward direction-2 sums sq, [NA][P][AS]; rh
     // the point values sh [NF][PG][TY][HS]; rb the forward direction-2
-    // results sb and then the backward direction-1 sums sr, [NF][PG][TY][BS].
-    // With one group ra lies inside rh (sa is dead before sh is written, sh
-    // before sq).
+    // results sb and then (without ATOM2) the backward direction-1 sums and
+    // the per-element backward direction-2 rows, [NF][PG][TY][BS].  With one
+    // group ra lies inside rh (sa is dead before sh is written, sh before
+    // sq), and with ATOM2 sq lies in rb (see below).
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *xw = reinterpret_cast<CT *>(smem_raw);
     CT *yw = xw + P * NXY;
