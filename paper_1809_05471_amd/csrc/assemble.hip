@@ -192,7 +192,7 @@ __device__ __forceinline__ int comp3(int i, int j)
 // (c1, c2), c = n - m + p - 1.
 // L2M: level 2 on the vector ALU (0), on FP64 matrix cores (1), on bf16
 // matrix cores with split operands and FP32 accumulation (2).
-template <int P, bool STIFF, typename CT, int L2M>
+template <int P, bool STIFF, typename CT, int L2M, bool UNR = true>
 __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__restrict__ C, CT *__restrict__ A2,
                                             int q3base, int T1r, int bx, int by)
 {
@@ -210,8 +210,10 @@ __device__ __forceinline__ void asm12_block(const PatchView &pv, const CT *__res
     // level 2 on the vector ALU: two iterations in flight hide one LDS
     // latency each (order 6, 128^3 elements: FP64 79.7 -> 72.3 ms, FP32 level
     // 2 only 72.1 -> 70.0 ms); elsewhere the registers cost more than that
-    constexpr int U1 = (P == 6 && sizeof(CT) == sizeof(double)) ? 2 : 1;
-    constexpr int U2 = P == 6 ? 2 : 1;
+    // (single-patch kernel only: in the persistent kernel the registers
+    // cost more, batched FP64 93.2 against 89.7 ms)
+    constexpr int U1 = (UNR && P == 6 && sizeof(CT) == sizeof(double)) ? 2 : 1;
+    constexpr int U2 = (UNR && P == 6) ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT *cs = reinterpret_cast<CT *>(smem_raw);          // [NCOMP][g2][g1][XE]
     CT *l1 = cs + S::NSLICE;                            // [g2][pair][T1][W]
@@ -1079,7 +1081,8 @@ __global__ __launch_bounds__((A12Shape<P, STIFF, L2M>::NT), (A12Shape<P, STIFF, 
         const int t = task_of(tl.off, tl.ntask, it);
         const BatchTask &T = tl.tasks[t];
         const int64_t l = it - tl.off[t];
-        asm12_block<P, STIFF, CT, L2M>(T.pv, (const CT *)T.C, (CT *)T.ws, 0, T.arg, (int)(l % T.gx), (int)(l / T.gx));
+        asm12_block<P, STIFF, CT, L2M, false>(T.pv, (const CT *)T.C, (CT *)T.ws, 0, T.arg, (int)(l % T.gx),
+                                              (int)(l / T.gx));
         __syncthreads();   // LDS of the next block
     }
 }
