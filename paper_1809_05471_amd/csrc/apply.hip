@@ -729,6 +729,7 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
     constexpr bool FOLD1 = E <= P;
     constexpr bool ATOM2 = FOLD1 && sizeof(CT) == sizeof(double);
     constexpr int NQ2 = STIFF ? 3 : 1;     // output fields of forward direction 2 (one item each)
+    constexpr bool MERGE3 = ATOM2 && G == 1 && CM == 2;
     static_assert(!(ATOM2 && G == 1) || NA * P * AS <= NF * SBF, "sq fits in rb");
     CT *sq = (ATOM2 && G == 1) ? rb : ra;
     CT *t3Wb = rb + NF * SBF;              // direction-3 weights, [layer parity][g] (FP16 split)
@@ -883,7 +884,43 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
         store_t3(e3a);
         load_planes(e3a, 0, P);
     }
+    // ---- F3 of layer e: a = B3 x, b = D3 x into sa, per function column and
+    // group of planes.  With MERGE3 it runs in the last stage of the previous
+    // layer, beside backward direction 3 (they touch different buffers: sq
+    // lies in rb, sa in rh, and the x window of layer e is complete once the
+    // previous layer's first stage stored its last row), which saves one
+    // barrier per layer.
+    auto forward3 = [&](int e, const CT *t3Le, uniform_ptr<CT> T3Be, uniform_ptr<CT> T3De) {
+        auto tb3 = [&](int i) -> CT { if constexpr (T3L) return t3Le[i]; else return T3Be[i]; };
+        auto td3 = [&](int i) -> CT { if constexpr (T3L) return t3Le[PP + i]; else return T3De[i]; };
+        for (int idx = thread_index(); idx < RM::GS * RM::RXY; idx += NT) {
+            const int grp = __builtin_amdgcn_readfirstlane(idx / RM::RXY), j = idx % RM::RXY;
+            if (j < NXY) {
+                CT v[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) v[s] = xw[((e + s) % P) * NXY + j];
+#pragma unroll
+                for (int k = 0; k < RM::PG3; ++k) {
+                    const int g3 = grp * RM::PG3 + k;
+                    if (g3 < P) {
+                        CT a = CT(0), b = CT(0);
+#pragma unroll
+                        for (int s = 0; s < P; ++s) {
+                            a += tb3(g3 * P + s) * v[s];
+                            if (STIFF) b += td3(g3 * P + s) * v[s];
+                        }
+                        ra[g3 * AS + j] = a;
+                        if (STIFF) ra[(P + g3) * AS + j] = b;
+                    }
+                }
+            }
+        }
+    };
     __syncthreads();
+    if constexpr (MERGE3) {
+        forward3(e3a, t3s + (e3a & 1) * 2 * PP, elem_table(B3g, e3a, d2.K, PP), elem_table(D3g, e3a, d2.K, PP));
+        __syncthreads();
+    }
 
     for (int e3 = e3a; e3 <= e3z; ++e3) {
         const bool more = e3 < e3z;
@@ -898,30 +935,11 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
         auto t3b = [&](int i) -> CT { if constexpr (T3L) return t3L[i]; else return T3Bs[i]; };
         auto t3d = [&](int i) -> CT { if constexpr (T3L) return t3L[PP + i]; else return T3Ds[i]; };
 
-        // ---- F3: a = B3 x, b = D3 x, per function column and group of planes
-        for (int idx = thread_index(); idx < RM::GS * RM::RXY; idx += NT) {
-            const int grp = __builtin_amdgcn_readfirstlane(idx / RM::RXY), j = idx % RM::RXY;
-            if (j < NXY) {
-                CT v[P];
-#pragma unroll
-                for (int s = 0; s < P; ++s) v[s] = xw[((e3 + s) % P) * NXY + j];
-#pragma unroll
-                for (int k = 0; k < RM::PG3; ++k) {
-                    const int g3 = grp * RM::PG3 + k;
-                    if (g3 < P) {
-                        CT a = CT(0), b = CT(0);
-#pragma unroll
-                        for (int s = 0; s < P; ++s) {
-                            a += t3b(g3 * P + s) * v[s];
-                            if (STIFF) b += t3d(g3 * P + s) * v[s];
-                        }
-                        ra[g3 * AS + j] = a;
-                        if (STIFF) ra[(P + g3) * AS + j] = b;
-                    }
-                }
-            }
+        // ---- F3 (without MERGE3; with it, the previous layer's last stage ran it)
+        if constexpr (!MERGE3) {
+            forward3(e3, t3L, T3Bs, T3Ds);
+            __syncthreads();
         }
-        __syncthreads();
         // the slot of x row e3 is free now
         if (more) {
             const int tid = thread_index();
@@ -1224,6 +1242,9 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
             }
             }
             if constexpr (CM == 2) load_planes(e3 + 1, 2 * P / 3, P);
+            if constexpr (MERGE3) {
+                if (more) store_t3(e3 + 1);   // read by the next layer's F3 in the last stage
+            }
             __syncthreads();
             // then (without ATOM2) per function row the sum over the <= p
             // elements that share it, into sq
@@ -1275,7 +1296,11 @@ __device__ __forceinline__ void apply3d_rows_block(const PatchView &pv, const CS
                 }
             }
         }
-        if (more) store_t3(e3 + 1);
+        if constexpr (MERGE3) {
+            if (more) forward3(e3 + 1, t3s + ((e3 + 1) & 1) * 2 * PP, T3Bs, T3Ds);
+        } else {
+            if (more) store_t3(e3 + 1);
+        }
         __syncthreads();
         // ---- row e3 is complete for this box
         flush_yrow(e3);
