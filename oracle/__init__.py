@@ -14,10 +14,12 @@ What it computes (all FP64, plain, unblocked):
   (degree + 1), as in Sec. 3.2 ("degree nu, order nu+1").
 * Gauss-Legendre rule with ``p`` points per element and direction (Example
   "Gauss quadrature" in Sec. 3.2), from ``numpy.polynomial.legendre.leggauss``.
-* Element-by-element quadrature sums of the mass and stiffness forms
-  (eq. (quadrature:1), pull-back of Example 1) in ``orc.c``; rows are test
-  functions, columns trial functions, lexicographic with direction 1 fastest
-  (Sec. 3.1).
+* Element-by-element quadrature sums of the mass, stiffness and convection
+  forms (eq. (quadrature:1), pull-back of Example 1) in ``orc.c``; rows are
+  test functions, columns trial functions, lexicographic with direction 1
+  fastest (Sec. 3.1).  The convection form is the b . grad u term of Example
+  1's equation tested with v (derivative on the trial function), with a
+  constant vector b scaled by the scalar coefficient.
 
 Readings of the paper adopted here (see the design notes of the repository):
 order notation, p Gauss points per element, open knot vectors, the
@@ -42,6 +44,7 @@ _LIB_PATH = os.path.join(_HERE, "liborc.so")
 
 MASS = 1
 STIFF = 2
+CONV = 4
 
 
 def build(force: bool = False) -> str:
@@ -76,6 +79,8 @@ def _lib():
                                               ctypes.c_int]
     lib.orc_eval.argtypes = prob + [f64p, f64p, f64p, f64p, ctypes.c_int]
     lib.orc_measure.argtypes = prob + [f64p]
+    lib.orc_set_convection.argtypes = [ctypes.c_double] * 3
+    lib.orc_set_convection.restype = None
     for f in (lib.orc_pattern, lib.orc_assemble, lib.orc_rows, lib.orc_apply_rows,
               lib.orc_apply, lib.orc_apply_elements, lib.orc_eval, lib.orc_measure):
         f.restype = ctypes.c_int
@@ -205,10 +210,13 @@ class Problem:
     """A single tensor-product patch: knot vectors, order per direction,
     control points [N, d] (lexicographic, direction 1 fastest) and a
     coefficient: ``("const", value)`` or ``("sinprod", alpha)`` meaning
-    1 + alpha * prod_i sin(2 pi x_i) at the physical point."""
+    1 + alpha * prod_i sin(2 pi x_i) at the physical point.  The stiffness
+    and convection forms take that coefficient, the mass form c = 1;
+    ``conv_b`` is the constant vector b of the convection form."""
 
-    def __init__(self, knots, orders, ctrl, coef=("const", 1.0)):
+    def __init__(self, knots, orders, ctrl, coef=("const", 1.0), conv_b=(0.0, 0.0, 0.0)):
         self.d = len(knots)
+        self.conv_b = [float(v) for v in conv_b] + [0.0] * (3 - len(conv_b))
         if isinstance(orders, int):
             orders = [orders] * self.d
         self.orders = list(orders)
@@ -234,6 +242,7 @@ class Problem:
         P = ctypes.POINTER
         i32 = P(ctypes.c_int32)
         f64 = P(ctypes.c_double)
+        _lib().orc_set_convection(*self.conv_b[:3])
         return [self.d, self._p.ctypes.data_as(i32), self._nel.ctypes.data_as(i32),
                 self._nf.ctypes.data_as(i32), self._first.ctypes.data_as(i32),
                 self._w.ctypes.data_as(f64), self._phi.ctypes.data_as(f64),
@@ -263,7 +272,8 @@ class Problem:
         return rp, ci
 
     def assemble(self, op, threads=0, pattern=None):
-        """Full CSR (row_ptr, col_ind, values) of the mass (op=1) or stiffness (op=2) matrix."""
+        """Full CSR (row_ptr, col_ind, values) of the mass (op=1), stiffness
+        (op=2) or convection (op=4) matrix."""
         rp, ci = pattern if pattern is not None else self.pattern()
         vals = np.zeros(len(ci))
         kind, val = self._coef_for(op)

@@ -13,6 +13,14 @@
  *   mass      M[m][n] = sum_x  w(x) c(G(x)) |det J(x)| phi_n(x) phi_m(x)
  *   stiffness K[m][n] = sum_x  w(x) a(G(x)) |det J(x)|
  *                             (J^-T grad phi_n)(x) . (J^-T grad phi_m)(x)
+ *   convection B[m][n] = sum_x w(x) s(G(x)) |det J(x)|
+ *                             (b . J^-T grad phi_n)(x) phi_m(x)
+ *
+ * (op 1, 2, 4).  The convection term is the b . grad u of the
+ * convection-diffusion equation of Example 1, tested with v: the derivative
+ * falls on the trial function n, the value on the test function m, so B is
+ * not symmetric.  b is a constant vector (orc_set_convection) scaled by the
+ * scalar coefficient s.
  *
  * with J_ik = dG_i / dxhat_k, G = sum_n c_n phi_n (Sec. 6.3).  Rows are test
  * functions m, columns trial functions n (Sec. 2, matrix definition), both
@@ -135,6 +143,23 @@ static int prob_init(prob_t *P, int d, const int *p, const int *nel, const int *
 static int orc_defect = 0;
 
 void orc_set_defect(int k) { orc_defect = k; }
+
+/* the constant vector b of the convection form (op 4) */
+static double orc_conv_b[MAXD] = {0.0, 0.0, 0.0};
+void orc_set_convection(double b1, double b2, double b3)
+{
+    orc_conv_b[0] = b1;
+    orc_conv_b[1] = b2;
+    orc_conv_b[2] = b3;
+}
+
+/* b . (J^-T grad_hat phi_l): the convection derivative of active function l */
+static inline double conv_deriv(const prob_t *P, const double *grad)
+{
+    double t = 0.0;
+    for (int i = 0; i < P->d; ++i) t += orc_conv_b[i] * grad[i];
+    return t;
+}
 
 static double coefficient(const prob_t *P, const double *x)
 {
@@ -375,6 +400,9 @@ int orc_assemble(PROB_ARGS, int op, const int64_t *row_ptr, double *vals, int nt
                         double t;
                         if (op == 1) {
                             t = Q->val[b] * Q->val[a];
+                        } else if (op == 4) {
+                            t = orc_defect == 6 ? conv_deriv(&P, Q->grad[a]) * Q->val[b]
+                                                : conv_deriv(&P, Q->grad[b]) * Q->val[a];
                         } else {
                             t = 0.0;
                             for (int i = 0; i < P.d; ++i) t += Q->grad[b][i] * Q->grad[a][i];
@@ -459,6 +487,8 @@ int orc_rows(PROB_ARGS, int op, int64_t nrows, const int64_t *rows, int maxband,
                     double t;
                     if (op == 1) {
                         t = Q->val[b] * Q->val[a];
+                    } else if (op == 4) {
+                        t = conv_deriv(&P, Q->grad[b]) * Q->val[a];
                     } else {
                         t = 0.0;
                         for (int k = 0; k < P.d; ++k) t += Q->grad[b][k] * Q->grad[a][k];
@@ -519,6 +549,10 @@ int orc_apply_rows(PROB_ARGS, int op, const double *x, int64_t nrows, const int6
                     double u = 0.0;
                     for (int b = 0; b < Q->nloc; ++b) u += x[Q->gidx[b]] * Q->val[b];
                     acc += s * u * Q->val[a];
+                } else if (op == 4) {
+                    double bu = 0.0;
+                    for (int b = 0; b < Q->nloc; ++b) bu += x[Q->gidx[b]] * conv_deriv(&P, Q->grad[b]);
+                    acc += s * bu * Q->val[a];
                 } else {
                     double gu[MAXD] = {0, 0, 0};
                     for (int b = 0; b < Q->nloc; ++b)
@@ -583,6 +617,10 @@ int orc_apply(PROB_ARGS, int op, const double *x, double *y, int nthreads)
                     double u = 0.0;
                     for (int b = 0; b < Q->nloc; ++b) u += x[Q->gidx[b]] * Q->val[b];
                     for (int a = 0; a < Q->nloc; ++a) y[Q->gidx[a]] += s * u * Q->val[a];
+                } else if (op == 4) {
+                    double bu = 0.0;
+                    for (int b = 0; b < Q->nloc; ++b) bu += x[Q->gidx[b]] * conv_deriv(&P, Q->grad[b]);
+                    for (int a = 0; a < Q->nloc; ++a) y[Q->gidx[a]] += s * bu * Q->val[a];
                 } else {
                     double gu[MAXD] = {0, 0, 0};
                     for (int b = 0; b < Q->nloc; ++b)
@@ -653,6 +691,10 @@ int orc_apply_elements(PROB_ARGS, int op, const double *x, int64_t nlist, const 
                     double u = 0.0;
                     for (int b = 0; b < Q->nloc; ++b) u += x[Q->gidx[b]] * Q->val[b];
                     for (int a = 0; a < Q->nloc; ++a) y[Q->gidx[a]] += s * u * Q->val[a];
+                } else if (op == 4) {
+                    double bu = 0.0;
+                    for (int b = 0; b < Q->nloc; ++b) bu += x[Q->gidx[b]] * conv_deriv(&P, Q->grad[b]);
+                    for (int a = 0; a < Q->nloc; ++a) y[Q->gidx[a]] += s * bu * Q->val[a];
                 } else {
                     double gu[MAXD] = {0, 0, 0};
                     for (int b = 0; b < Q->nloc; ++b)

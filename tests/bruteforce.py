@@ -31,8 +31,9 @@ def basis_1d(knots, p, x):
     return np.nan_to_num(V), np.nan_to_num(D)
 
 
-def dense_bruteforce(knots_list, p, ctrl, coef, op):
-    """Dense mass (op=1, coefficient 1) or stiffness (op=2) matrix."""
+def dense_bruteforce(knots_list, p, ctrl, coef, op, conv_b=None):
+    """Dense mass (op=1, coefficient 1), stiffness (op=2) or convection
+    (op=4: b . grad u tested with v, b = coefficient * conv_b) matrix."""
     d = len(knots_list)
     Xs, Ws, Vs, Ds = [], [], [], []
     for kn in knots_list:
@@ -62,6 +63,15 @@ def dense_bruteforce(knots_list, p, ctrl, coef, op):
         F = w * a * np.abs(det)
         return Qval.T @ (F[:, None] * Qval)
     a = np.full(len(w), val) if kind == "const" else 1 + val * np.prod(np.sin(2 * np.pi * G), axis=1)
+    if op == 4:
+        # physical gradient of phi_n: J^-T grad_hat phi_n; row m carries phi_m
+        b = np.asarray(conv_b, dtype=np.float64)[:d]
+        A = np.zeros((Qval.shape[1],) * 2)
+        for i in range(d):
+            # (J^-T g)_i = sum_k Jinv[k, i] g_k
+            gi = sum(Jinv[:, k, i][:, None] * Qder[k] for k in range(d))
+            A += Qval.T @ ((w * a * np.abs(det) * b[i])[:, None] * gi)
+        return A
     C = (w * a * np.abs(det))[:, None, None] * np.einsum("qij,qkj->qik", Jinv, Jinv)
     A = np.zeros((Qval.shape[1],) * 2)
     for i in range(d):

@@ -4,12 +4,14 @@ one pin fail, and the pins pass again once it is removed.
 Planted mistakes: 1 pull-back with J^-1 in place of J^-T (the transpose
 question of Example 1), 2 a dropped quadrature weight, 3 a dropped |det J|,
 4 a sign slip in the inverse, 5 the coefficient evaluated away from the
-physical point G(xhat).
+physical point G(xhat), 6 the convection derivative on the test function
+instead of the trial function (full assembly only).
 """
 import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_conv as conv_pins
 from tests import test_oracle_pins as pins
 
 PIN_CASES = [
@@ -22,10 +24,19 @@ PIN_CASES = [
     ("linear functions, evaluation", lambda: pins.test_eval_reproduces_linear_physical_functions(3, (3, 2, 4), 2)),
 ]
 
+# the convection form's pins, with the plants that touch it
+CONV_PIN_CASES = [
+    ("convection 1D by parts", lambda: conv_pins.test_1d_integration_by_parts(7, 3)),
+    ("convection identity Kronecker", lambda: conv_pins.test_identity_map_is_kronecker((3, 2, 3), 3)),
+    ("convection affine map 2D", lambda: conv_pins.test_affine_map_2d(np.array([[1.0, 0.3], [0.2, 1.1]]))),
+    ("convection coordinate function",
+     lambda: conv_pins.test_coordinate_function_on_curved_maps(3, (3, 2, 3), 2, ("const", 0.8))),
+]
 
-def _failing_pins():
+
+def _failing_pins(cases=PIN_CASES):
     failed = []
-    for name, case in PIN_CASES:
+    for name, case in cases:
         try:
             case()
         except (AssertionError, oracle.OracleError):
@@ -50,3 +61,16 @@ def test_planted_mistake_is_caught(planted, defect):
 def test_pins_pass_without_plant(planted):
     planted(0)
     assert _failing_pins() == []
+
+
+@pytest.mark.parametrize("defect", [1, 2, 3, 4, 6])
+def test_planted_mistake_is_caught_by_the_convection_pins(planted, defect):
+    planted(defect)
+    failed = _failing_pins(CONV_PIN_CASES)
+    planted(0)
+    assert failed, f"planted mistake {defect} passed every convection pin"
+
+
+def test_convection_pins_pass_without_plant(planted):
+    planted(0)
+    assert _failing_pins(CONV_PIN_CASES) == []
