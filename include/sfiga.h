@@ -16,6 +16,11 @@
  *        M[m][n] = sum_x w(x) c(G(x)) |det J| phi_n phi_m
  *        K[m][n] = sum_x w(x) a(G(x)) |det J| (J^-T grad phi_n).(J^-T grad phi_m)
  *     with J_ik = dG_i/dxhat_k;
+ *   - the convection form of the same example, the b . grad u term of the
+ *     equation tested with v (d = 3, FP64, matrix-free apply only):
+ *        B[m][n] = sum_x w(x) s(G(x)) |det J| (b . J^-T grad phi_n) phi_m
+ *     with a constant vector b and a scalar coefficient s; B is not
+ *     symmetric (the derivative falls on the trial function n);
  *   - outputs: the matrix in CSR form (global sum factorization, Algorithm 1)
  *     or the product y = A x (matrix-free, Algorithms 2 and 3).
  *
@@ -84,8 +89,9 @@ typedef enum {
                               entry points return SF_EUNSUPPORTED. */
 } sf_precision;
 
-/* operator bit flags */
-enum { SF_MASS = 1u, SF_STIFF = 2u };
+/* operator bit flags (SF_CONV: the convection form, accepted by
+ * sf_patch_set_coef, sf_patch_prepare and sf_apply only) */
+enum { SF_MASS = 1u, SF_STIFF = 2u, SF_CONV = 4u };
 
 typedef enum {
     SF_COEF_CONST = 0,     /* params[0] = constant value */
@@ -156,13 +162,20 @@ sf_status sf_patch_create(sf_ctx *ctx, const sf_patch_desc *desc, sf_patch **out
  * #NZ), number of quadrature points Q.  Any pointer may be NULL. */
 sf_status sf_patch_info(const sf_patch *patch, int64_t *ndof, int64_t *nnz, int64_t *nquad);
 
-/* Coefficient of operator `op` (exactly one of SF_MASS, SF_STIFF): the
- * reaction coefficient c for the mass form, the scalar diffusion a for the
- * stiffness form (Example 1 with A = a I).  For SF_COEF_CONST and
- * SF_COEF_SINPROD `params` is a host pointer to one double; for
- * SF_COEF_QPVALUES it is a device pointer to Q doubles, which must stay
- * valid until the next sf_patch_prepare.  Default: constant 1 for both. */
+/* Coefficient of operator `op` (exactly one of SF_MASS, SF_STIFF, SF_CONV):
+ * the reaction coefficient c for the mass form, the scalar diffusion a for
+ * the stiffness form (Example 1 with A = a I), the scalar s of the
+ * convection velocity s(x) b.  For SF_COEF_CONST and SF_COEF_SINPROD
+ * `params` is a host pointer to one double; for SF_COEF_QPVALUES it is a
+ * device pointer to Q doubles, which must stay valid until the next
+ * sf_patch_prepare.  Default: constant 1 for all three. */
 sf_status sf_patch_set_coef(sf_patch *patch, unsigned op, sf_coef_kind kind, const double *params);
+
+/* The constant vector b of the convection form (Sec. 2, Example 1: the
+ * b . grad u term), host pointer to d doubles in physical coordinates;
+ * the velocity is s(x) b with s set by sf_patch_set_coef(SF_CONV).
+ * Default b = 0.  Takes effect at the next sf_patch_prepare of SF_CONV. */
+sf_status sf_patch_set_convection(sf_patch *patch, const double *b);
 
 /* Physical coordinates G(x) of all quadrature points, device [Q][d],
  * lexicographic with quadrature direction 1 fastest (for SF_COEF_QPVALUES
@@ -185,9 +198,11 @@ sf_status sf_patch_eval(sf_patch *patch, const double *dev_u, double *dev_val, d
 /* Geometry step (Sec. 6.3): evaluates G and its Jacobian at all quadrature
  * points by sum factorization (Algorithm 3), and folds weight, coefficient,
  * |det J| and J^-1 J^-T into the quadrature-coefficient tensor of each
- * operator in `ops`, stored at `prec`.  Synchronises once and returns
- * SF_EGEOM if det J <= 0 anywhere.  Must precede assemble/apply of an
- * operator at a precision; repeating it is allowed (recomputes). */
+ * operator in `ops`, stored at `prec` (SF_CONV: w s |det J| J^-1 b, three
+ * components per point, d = 3 and SF_FP64 only, else SF_EUNSUPPORTED).
+ * Synchronises once and returns SF_EGEOM if det J <= 0 anywhere.  Must
+ * precede assemble/apply of an operator at a precision; repeating it is
+ * allowed (recomputes). */
 sf_status sf_patch_prepare(sf_patch *patch, unsigned ops, sf_precision prec);
 
 /* sf_patch_prepare without the synchronisation (Sec. 6.3, as above): queues
@@ -209,6 +224,7 @@ sf_status sf_patch_geometry_check(sf_patch *patch);
 sf_status sf_csr_pattern(sf_patch *patch, int64_t *dev_row_ptr, int32_t *dev_col_ind);
 
 /* Global sum-factorized assembly (Algorithm 1) of the operators in `ops`
+ * (SF_MASS, SF_STIFF; SF_CONV returns SF_EUNSUPPORTED)
  * into the values of the sf_csr_pattern() layout: dev_val_mass and/or
  * dev_val_stiff, device [nnz] FP64 (the pointer of an operator not in ops
  * is ignored).  Needs a prior sf_patch_prepare of those operators at
@@ -251,7 +267,13 @@ sf_status sf_assemble_noalloc(sf_patch *patch, unsigned ops, sf_precision prec,
  * of op at `prec`.  Accumulates through FP64 atomics, so the last bits may
  * vary between runs.  Asynchronous, except that for d = 3 the first call per
  * (operator, precision) times a few workgroup shapes on this patch (writing
- * into dev_y, then overwriting it) and synchronizes once. */
+ * into dev_y, then overwriting it) and synchronizes once.
+ * op = SF_CONV (d = 3, SF_FP64): the convection form; Algorithm 3 forward
+ * with the derivative table in one direction at a time gives the three
+ * reference derivatives of x at every point, dotted with the folded
+ * coefficients into a point buffer (Q doubles plus tile padding, allocated
+ * by the first call and kept with the patch; SF_ENOMEM/SF_EDEVICE if that
+ * fails), then Algorithm 2 backward with value tables; no tuning. */
 sf_status sf_apply(sf_patch *patch, unsigned op, sf_precision prec, const double *dev_x, double *dev_y);
 
 /* Release the patch and its device workspace (synchronises its stream). */
@@ -283,7 +305,8 @@ sf_status sf_batch_assemble(sf_batch *batch, unsigned ops, sf_precision prec, in
                             int32_t *dev_col_ind, double *dev_val_mass, double *dev_val_stiff);
 
 /* y = blockdiag(A_b) x over the concatenated vectors; persistent kernels,
- * graph capture and first-call tuning as for sf_batch_assemble. */
+ * graph capture and first-call tuning as for sf_batch_assemble (SF_MASS,
+ * SF_STIFF; SF_CONV returns SF_EUNSUPPORTED). */
 sf_status sf_batch_apply(sf_batch *batch, unsigned op, sf_precision prec, const double *dev_x,
                          double *dev_y);
 

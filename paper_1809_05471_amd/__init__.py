@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsfiga.so")
 
 SF_OK, SF_EINVAL, SF_EKNOT, SF_EGEOM, SF_ENOMEM, SF_EDEVICE, SF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SF_FP64, SF_FP32, SF_BF16_SPLIT, SF_FP16_SPLIT = 0, 1, 2, 3
-SF_MASS, SF_STIFF = 1, 2
+SF_MASS, SF_STIFF, SF_CONV = 1, 2, 4
 SF_COEF_CONST, SF_COEF_SINPROD, SF_COEF_QPVALUES = 0, 1, 2
 
 STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4: "SF_ENOMEM",
@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4:
 
 EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target", "sf_host_tables_1d",
             "sf_patch_create",
-            "sf_patch_info", "sf_patch_set_coef", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
+            "sf_patch_info", "sf_patch_set_coef", "sf_patch_set_convection", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
             "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_assemble_noalloc", "sf_apply", "sf_patch_destroy", "sf_batch_create",
             "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_batch_destroy"]
 
@@ -61,6 +61,7 @@ def lib():
         "sf_patch_create": (st, [vp, ctypes.POINTER(PatchDesc), ctypes.POINTER(vp)]),
         "sf_patch_info": (st, [vp, i64p, i64p, i64p]),
         "sf_patch_set_coef": (st, [vp, ctypes.c_uint, ctypes.c_int, vp]),
+        "sf_patch_set_convection": (st, [vp, vp]),
         "sf_patch_quad_points": (st, [vp, vp]),
         "sf_patch_eval": (st, [vp, vp, vp, vp]),
         "sf_patch_prepare": (st, [vp, ctypes.c_uint, ctypes.c_int]),
@@ -182,6 +183,11 @@ def sf_patch_set_coef(ctx, patch, op, kind, value=None, qp_values=None):
     else:
         v = (ctypes.c_double * 1)(float(value))
         _check(lib().sf_patch_set_coef(patch, op, kind, ctypes.cast(v, ctypes.c_void_p)), ctx)
+
+
+def sf_patch_set_convection(ctx, patch, b):
+    v = (ctypes.c_double * len(b))(*[float(t) for t in b])
+    _check(lib().sf_patch_set_convection(patch, ctypes.cast(v, ctypes.c_void_p)), ctx)
 
 
 def sf_patch_quad_points(ctx, patch, xyz):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsfiga.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["spline.cpp", "sfiga.cpp", "geom.hip", "pattern.hip", "apply.hip", "assemble.hip"]
+SOURCES = ["spline.cpp", "sfiga.cpp", "geom.hip", "pattern.hip", "apply.hip", "assemble.hip", "conv.hip"]
 ARCH = "gfx950"
 
 

@@ -5,6 +5,7 @@
 // coefficients (Example 1 with A = a I):
 //   mass:      w c |det J|
 //   stiffness: w a |det J| (J^-1 J^-T)_ij, i <= j   (J_ik = dG_i/dxhat_k)
+//   convection: w s |det J| (J^-1 b)_k, k = 1..3 (b . grad u = (J^-1 b) . grad_hat u)
 #include <hip/hip_fp16.h>
 
 #include "kernels.h"
@@ -59,6 +60,12 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
             idx = apply_coef_index(1, 0, q0, q1, q2, P, K0, Q2);
             if (f32) store_coef<float>(o.ca_mass, idx, v); else store_coef<double>(o.ca_mass, idx, v);
         }
+    }
+    if (o.c_conv) {
+        const double s = wd * eval_coef(o.coef_conv, G, 3, qlin);
+        for (int k = 0; k < 3; ++k)
+            o.c_conv[conv_coef_index(k, q0, q1, q2, P, K0, Q2)] =
+                s * (inv[k][0] * o.bconv[0] + inv[k][1] * o.bconv[1] + inv[k][2] * o.bconv[2]);
     }
     if (o.c_stiff) {
         double s = wd * eval_coef(o.coef_stiff, G, 3, qlin);

@@ -72,6 +72,20 @@ __host__ __device__ inline int64_t apply_coef_size(int ncomp, int P, int K0, int
     return gx * gy * (int64_t)K2 * P * ncomp * T * T;
 }
 
+// Convection coefficient layout (d = 3): the tiles of apply_coef_index, per
+// tile and quadrature plane q3 the three components one after another, each
+// the tile's T x T columns (row ty, column tx).  The point buffer between the
+// two convection kernels is the same with one component (apply_coef_index
+// with ncomp = 1).  Columns outside the patch hold 0.
+__host__ __device__ inline int64_t conv_coef_index(int comp, int q0, int q1, int q2, int P, int K0, int Q2)
+{
+    const int T = apply_tile_elems(P) * P;
+    const int gx = (K0 * P + T - 1) / T;
+    const int bx = q0 / T, by = q1 / T;
+    const int64_t tile = (int64_t)by * gx + bx;
+    return ((tile * Q2 + q2) * 3 + comp) * (T * T) + (int64_t)(q1 - by * T) * T + (q0 - bx * T);
+}
+
 struct PatchView {
     int d, P;
     Dir dir[3];            // unused directions: K = N = Q = 1, tables null
@@ -87,7 +101,9 @@ struct GeomOut {
     void *ca_mass;         // the same in the apply's tiled layout (apply_coef_index, d = 3), or null
     void *ca_stiff;
     double *xyz;           // [Q][d] physical quadrature points, or null
-    Coef coef_mass, coef_stiff;
+    double *c_conv;        // convection, FP64 in the layout of conv_coef_index (d = 3), or null
+    Coef coef_mass, coef_stiff, coef_conv;
+    double bconv[3];       // the convection vector b (scaled by coef_conv)
     int *bad_det;          // device flag set to 1 if det J <= 0 somewhere, or null
     Prec prec;
     // evaluation of a discrete function u = sum_n u_n phi_n (Algorithm 3):
@@ -182,6 +198,11 @@ hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, c
 // true if the d = 3 apply of op at prec and order P reads its coefficients
 // in the tiled layout (the geometry step then writes that copy as well)
 bool apply_tiled_layout(int P, int op, Prec prec);
+// Convection product y = B x (d = 3, FP64): cv the folded coefficients
+// (conv_coef_index layout), h a point buffer of apply_coef_size(1, ...)
+// doubles; y is overwritten.
+hipError_t launch_conv_apply(const PatchView &pv, const double *cv, double *h, const double *x, double *y,
+                             hipStream_t s);
 // F16S storage from the FP32 coefficient tensor c32 of op (d = 3): per element
 // and component the reference r = (max + min) / 2 and scale s = (max - min) / 2
 // of C / w over the element's points (rs [K3][K2][K1][ncomp][2]), and per point

@@ -48,6 +48,13 @@ struct sf_patch {
     // by the geometry step beside C
     void *CA[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool assembly_only = false;          // the relabelled copy of a patch: no apply
+    // convection form (d = 3, FP64, matrix-free apply only): scalar
+    // coefficient s and vector b, folded coefficients w s |det J| J^-1 b
+    // (conv_coef_index layout) and the point buffer between its two kernels
+    Coef coef_conv{0, 1.0, nullptr};
+    double bconv[3] = {0.0, 0.0, 0.0};
+    double *Cv = nullptr, *hconv = nullptr;
+    bool conv_ready = false;
     bool ready[2][4] = {};               // [op][precision mode]
     // level-2 workspace of the d = 3 assembly, sized once for the largest
     // (operator, precision) so that captured graphs never see it move
@@ -176,6 +183,8 @@ void free_patch_memory(sf_patch *p)
     for (auto &a : p->CA)
         for (void *c : a) (void)hipFree(c);
     for (float *r : p->rs) (void)hipFree(r);
+    (void)hipFree(p->Cv);
+    (void)hipFree(p->hconv);
 }
 
 }  // namespace
@@ -349,7 +358,8 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
 {
     if (!p) return SF_EINVAL;
     sf_ctx *ctx = p->ctx;
-    if (op != SF_MASS && op != SF_STIFF) return fail(ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
+    if (op != SF_MASS && op != SF_STIFF && op != SF_CONV)
+        return fail(ctx, SF_EINVAL, "op must be SF_MASS, SF_STIFF or SF_CONV");
     if (!params) return fail(ctx, SF_EINVAL, "null params");
     Coef c{};
     switch (kind) {
@@ -357,6 +367,11 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
     case SF_COEF_SINPROD: c = Coef{1, params[0], nullptr}; break;
     case SF_COEF_QPVALUES: c = Coef{2, 0.0, params}; break;
     default: return fail(ctx, SF_EINVAL, "unknown coefficient kind");
+    }
+    if (op == SF_CONV) {
+        p->coef_conv = c;
+        p->conv_ready = false;
+        return SF_OK;
     }
     int oi = op == SF_MASS ? 0 : 1;
     p->coef[oi] = c;
@@ -369,6 +384,16 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
         if (c.kind == 2)
             for (int &o : p->order_sh[oi]) o = o > 0 ? 0 : o;
     }
+    return SF_OK;
+}
+
+sf_status sf_patch_set_convection(sf_patch *p, const double *b)
+{
+    if (!p) return SF_EINVAL;
+    p->ctx->err.clear();
+    if (!b) return fail(p->ctx, SF_EINVAL, "null vector");
+    for (int k = 0; k < 3; ++k) p->bconv[k] = k < p->d ? b[k] : 0.0;
+    p->conv_ready = false;
     return SF_OK;
 }
 
@@ -411,10 +436,14 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     if (!p) return SF_EINVAL;
     sf_ctx *ctx = p->ctx;
     ctx->err.clear();
-    if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
+    if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF | SF_CONV))) return fail(ctx, SF_EINVAL, "bad operator flags");
     int pi;
     if (!prec_index(prec, pi)) return fail(ctx, SF_EINVAL, "bad precision");
     if (pi == 3 && p->d != 3) return fail(ctx, SF_EUNSUPPORTED, "the FP16-split storage is built for d = 3");
+    if ((ops & SF_CONV) && (p->d != 3 || pi != 0 || p->assembly_only))
+        return fail(ctx, SF_EUNSUPPORTED, "the convection form is built for d = 3 at SF_FP64");
+    if ((ops & SF_CONV) && p->coef_conv.kind == 2 && !p->coef_conv.qp)
+        return fail(ctx, SF_EINVAL, "missing quadrature values");
     hipStream_t s = ctx->stream;
     const int gi = geom_storage(pi);
     const size_t esz = gi == 0 ? sizeof(double) : sizeof(float);
@@ -462,6 +491,21 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
         if (oi == 0) o.c_mass = p->C[oi][gi]; else o.c_stiff = p->C[oi][gi];
         if (tiled) (oi == 0 ? o.ca_mass : o.ca_stiff) = p->CA[oi][gi];
     }
+    if (ops & SF_CONV) {
+        if (!p->Cv) {
+            // columns outside the patch are never written: cleared once here
+            const size_t bytes = 3 * sizeof(double) * (size_t)apply_coef_size(1, p->P, p->view.dir[0].K,
+                                                                              p->view.dir[1].K, p->view.dir[2].K);
+            sf_status st = alloc((void **)&p->Cv, bytes);
+            if (st != SF_OK) return st;
+            hipError_t e0 = hipMemsetAsync(p->Cv, 0, bytes, s);
+            if (e0 != hipSuccess) return hip_fail(ctx, e0, "convection coefficients");
+        }
+        p->conv_ready = false;
+        o.c_conv = p->Cv;
+        o.coef_conv = p->coef_conv;
+        for (int k = 0; k < 3; ++k) o.bconv[k] = p->bconv[k];
+    }
     hipError_t e = sync ? hipMemsetAsync(p->dflag, 0, sizeof(int), s) : hipSuccess;
     if (e == hipSuccess) e = launch_geometry(p->view, o, s);
     if (pi == 3)
@@ -475,6 +519,7 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "geometry step");
     if (flag) return fail(ctx, SF_EGEOM, "det J <= 0 at some quadrature point");
+    if (ops & SF_CONV) p->conv_ready = true;
     for (int oi = 0; oi < 2; ++oi)
         if (ops & (oi == 0 ? SF_MASS : SF_STIFF)) {
             // FP32 storage serves FP32 and BF16 split; the FP16 split needs its own pass
@@ -531,6 +576,9 @@ sf_status sf_csr_pattern(sf_patch *p, int64_t *row_ptr, int32_t *col_ind)
 static sf_status check_ready(sf_patch *p, unsigned ops, sf_precision prec, int &pi, bool for_apply)
 {
     sf_ctx *ctx = p->ctx;
+    if (ops & SF_CONV)
+        return fail(ctx, SF_EUNSUPPORTED, "the convection form is built for the single-patch matrix-free "
+                                          "apply (sf_apply) only");
     if (ops == 0 || (ops & ~(unsigned)(SF_MASS | SF_STIFF))) return fail(ctx, SF_EINVAL, "bad operator flags");
     if (!prec_index(prec, pi)) return fail(ctx, SF_EINVAL, "bad precision");
     if (for_apply && pi == 2)
@@ -815,7 +863,27 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
 {
     if (!p) return SF_EINVAL;
     p->ctx->err.clear();
-    if (op != SF_MASS && op != SF_STIFF) return fail(p->ctx, SF_EINVAL, "op must be SF_MASS or SF_STIFF");
+    if (op == SF_CONV) {
+        if (prec != SF_FP64 || p->d != 3 || p->assembly_only)
+            return fail(p->ctx, SF_EUNSUPPORTED, "the convection form is built for d = 3 at SF_FP64");
+        if (!p->conv_ready)
+            return fail(p->ctx, SF_EINVAL, "operator not prepared at this precision (call sf_patch_prepare)");
+        if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
+        if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
+        if (!p->hconv) {
+            const size_t bytes = sizeof(double) * (size_t)apply_coef_size(1, p->P, p->view.dir[0].K,
+                                                                          p->view.dir[1].K, p->view.dir[2].K);
+            hipError_t e = hipMalloc((void **)&p->hconv, bytes);
+            if (e != hipSuccess) {
+                p->hconv = nullptr;
+                return hip_fail(p->ctx, e, "convection point buffer");
+            }
+        }
+        hipError_t e = launch_conv_apply(p->view, p->Cv, p->hconv, x, y, p->ctx->stream);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "convection kernels");
+        return SF_OK;
+    }
+    if (op != SF_MASS && op != SF_STIFF) return fail(p->ctx, SF_EINVAL, "op must be SF_MASS, SF_STIFF or SF_CONV");
     int pi;
     sf_status st = check_ready(p, op, prec, pi, true);
     if (st != SF_OK) return st;
