@@ -271,9 +271,8 @@ sf_status sf_assemble_noalloc(sf_patch *patch, unsigned ops, sf_precision prec,
  * op = SF_CONV (d = 3, SF_FP64): the convection form; Algorithm 3 forward
  * with the derivative table in one direction at a time gives the three
  * reference derivatives of x at every point, dotted with the folded
- * coefficients into a point buffer (Q doubles plus tile padding, allocated
- * by the first call and kept with the patch; SF_ENOMEM/SF_EDEVICE if that
- * fails), then Algorithm 2 backward with value tables; no tuning. */
+ * coefficients, then Algorithm 2 backward with value tables, in one kernel
+ * (no workspace, no tuning). */
 sf_status sf_apply(sf_patch *patch, unsigned op, sf_precision prec, const double *dev_x, double *dev_y);
 
 /* Release the patch and its device workspace (synchronises its stream). */

@@ -5,79 +5,102 @@
 // c folded per quadrature point by the geometry step (conv_coef_index
 // layout).  The trial side needs the three reference derivatives of u
 // (Algorithm 3 with the derivative table in one direction at a time), the
-// test side only values (Algorithm 2 with value tables), so the form is not
-// symmetric and is computed by a pair of kernels over the same grid (element
-// tile of E x E elements in directions 1 and 2, E = apply_tile_elems(P), one
-// element layer in direction 3 per workgroup):
-//   conv_forward_kernel   the tile's x block (E+p-1)^2 x p, contracted
-//                         3 -> 2 -> 1 through LDS into the three derivatives
-//                         at the tile's points, dotted with c, stored to the
-//                         point buffer h (one contiguous block per tile and
-//                         layer);
-//   conv_backward_kernel  h of the tile and layer, contracted with the value
-//                         tables 1 -> 2 -> 3 (the sums over the elements that
-//                         share a function formed inside the tile), added into
-//                         y with FP64 atomics (tiles and layers overlap in p-1
-//                         functions per direction).
-// HBM per quadrature point: c (24 B) and h written and read (16 B), plus
-// the x block and the y atomics (about 43 and 43 values per element at
-// order 6, E = 3).
+// test side only values (Algorithm 2 with value tables): the form is not
+// symmetric and has a kernel of its own.
+//
+// One workgroup per (tile of E x E elements in directions 1 and 2, element
+// layer e3), E = conv_tile_elems(P); everything between the loads of x and c
+// and the atomic adds into y stays in LDS:
+//   forward   the tile's x block ((E+p-1)^2 functions x p layers) contracted
+//             3 -> 2 -> 1 (B3/D3, then B2/D2, then D1/B1) into the three
+//             reference derivatives at the tile's points, dotted with c;
+//   backward  those point values contracted with the value tables 1 -> 2 -> 3
+//             (the sums over the elements that share a function formed inside
+//             the tile), added into y with FP64 atomics (tiles and layers
+//             overlap in p - 1 functions per direction).
+// The element tables of the tile are staged in LDS (a lane's table row
+// depends on its point, so global loads would go one per operand through
+// the vector memory path).  HBM per quadrature point: c, 24 bytes; the x
+// block and the y atomics add about ((E+p-1)/(E p))^2 of a value each per
+// point and layer.
 #include "kernels.h"
 
 namespace sfiga {
 
 template <int P>
 struct ConvTile {
-    static constexpr int E = apply_tile_elems(P);
-    static constexpr int T = E * P;         // quadrature points per tile side
-    static constexpr int NF = E + P - 1;    // functions per tile side
+    static constexpr int E = conv_tile_elems(P);
+    static constexpr int T = E * P;          // quadrature points per tile side
+    static constexpr int NF = E + P - 1;     // functions per tile side
     static constexpr int NT = 256;
+    static constexpr int PP = P * P, NFF = NF * NF, TT = T * T;
+    static constexpr int SB = P * T * NF;    // one field of the direction-2 results
+    // LDS in doubles: tables, x rows, direction-3 results, direction-2 results, point values
+    static constexpr int LDS = 4 * E * PP + 2 * PP + P * NFF + 2 * P * NFF + 3 * SB + P * TT;
 };
 
 template <int P>
-__global__ __launch_bounds__(256) void conv_forward_kernel(PatchView pv, const double *__restrict__ cv,
-                                                           const double *__restrict__ x, double *__restrict__ h)
+__global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *__restrict__ cv,
+                                                   const double *__restrict__ x, double *__restrict__ y)
 {
     using CT = ConvTile<P>;
-    constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, NFF = NF * NF, TT = T * T;
-    constexpr int SB = P * T * NF;           // one field of the direction-2 results
-    __shared__ double xs[P * NFF];           // x rows e3 .. e3+p-1 of the tile: [s][ly][lx]
-    __shared__ double sa[2 * P * NFF];       // B3 x, D3 x: [2][g3][ly][lx]
-    __shared__ double sb[3 * SB];            // B2 B3 x, D2 B3 x, B2 D3 x: [3][g3][yy][lx]
+    constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, PP = CT::PP, NFF = CT::NFF, TT = CT::TT;
+    constexpr int SB = CT::SB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *t1B = reinterpret_cast<double *>(smem_raw);   // [element l][point h][function j]
+    double *t1D = t1B + E * PP, *t2B = t1D + E * PP, *t2D = t2B + E * PP;
+    double *t3B = t2D + E * PP, *t3D = t3B + PP;           // [point g][function j] of layer e3
+    double *xs = t3D + PP;                                 // x rows e3 .. e3+p-1: [s][ly][lx]
+    double *sa = xs + P * NFF;     // B3 x, D3 x: [2][g3][ly][lx]; then the direction-2 sums r2 [g3][ly][lx]
+    double *sb = sa + 2 * P * NFF; // B2 B3 x, D2 B3 x, B2 D3 x: [3][g3][yy][lx]; then the direction-1 sums r1
+    double *hs = sb + 3 * SB;      // point values c . grad_hat u: [g3][yy][xx]
     const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
     const int bx = blockIdx.x, by = blockIdx.y, e3 = blockIdx.z;
     const int e1b = bx * E, e2b = by * E;
     const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
     const int tid = threadIdx.x;
 
+    // element tables (elements past the patch edge take the last element's:
+    // their points have c = 0 and their functions are not stored)
+    for (int i = tid; i < E * PP; i += NT) {
+        const int l = i / PP, r = i % PP;
+        const int64_t a1 = (int64_t)min(e1b + l, d0.K - 1) * PP + r;
+        const int64_t a2 = (int64_t)min(e2b + l, d1.K - 1) * PP + r;
+        t1B[i] = d0.B[a1];
+        t1D[i] = d0.D[a1];
+        t2B[i] = d1.B[a2];
+        t2D[i] = d1.D[a2];
+    }
+    for (int i = tid; i < PP; i += NT) {
+        t3B[i] = d2.B[(int64_t)e3 * PP + i];
+        t3D[i] = d2.D[(int64_t)e3 * PP + i];
+    }
     for (int i = tid; i < P * NFF; i += NT) {
         const int s = i / NFF, j = i % NFF;
         const int n0 = e1b + j % NF, n1 = e2b + j / NF;
         xs[i] = (n0 < d0.N && n1 < d1.N) ? x[n0 + N0 * n1 + N01 * (e3 + s)] : 0.0;
     }
     __syncthreads();
-    // direction 3: a = B3 x, b = D3 x per plane g3 and function column
-    const double *B3 = d2.B + (int64_t)e3 * P * P, *D3 = d2.D + (int64_t)e3 * P * P;
+    // ---- forward, direction 3: a = B3 x, b = D3 x per plane g3 and function column
     for (int i = tid; i < P * NFF; i += NT) {
         const int g3 = i / NFF, j = i % NFF;
         double a = 0.0, b = 0.0;
 #pragma unroll
         for (int s = 0; s < P; ++s) {
             const double v = xs[s * NFF + j];
-            a += B3[g3 * P + s] * v;
-            b += D3[g3 * P + s] * v;
+            a += t3B[g3 * P + s] * v;
+            b += t3D[g3 * P + s] * v;
         }
         sa[i] = a;
         sa[P * NFF + i] = b;
     }
     __syncthreads();
-    // direction 2, per point row yy = (element l2, point h2): B2 a (for d1),
-    // D2 a (d2), B2 b (d3)
+    // ---- direction 2, per point row yy = (element l2, point h2): B2 a (for
+    // d1), D2 a (d2), B2 b (d3)
     for (int i = tid; i < SB; i += NT) {
         const int lx = i % NF, yy = (i / NF) % T, g3 = i / (NF * T);
-        const int l2 = yy / P, h2 = yy % P;
-        const int e2 = min(e2b + l2, d1.K - 1);     // rows outside the patch: any table, results unused
-        const double *B2 = d1.B + ((int64_t)e2 * P + h2) * P, *D2 = d1.D + ((int64_t)e2 * P + h2) * P;
+        const int l2 = yy / P;
+        const double *B2 = t2B + yy * P, *D2 = t2D + yy * P;     // (l2 P + h2) P = yy P
         const double *ca = sa + g3 * NFF + l2 * NF + lx, *cb = ca + P * NFF;
         double f0 = 0.0, f1 = 0.0, f2 = 0.0;
 #pragma unroll
@@ -91,15 +114,13 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(PatchView pv, const d
         sb[2 * SB + i] = f2;
     }
     __syncthreads();
-    // direction 1 and the pointwise product, per point (g3, yy, xx)
+    // ---- direction 1 and the pointwise product, per point (g3, yy, xx)
     const int64_t tile = (int64_t)by * gridDim.x + bx;
-    const int64_t hb = (tile * d2.Q + (int64_t)e3 * P) * TT;           // first point of the layer
-    const int64_t cb0 = (tile * d2.Q + (int64_t)e3 * P) * 3 * TT;
+    const double *cl = cv + (tile * d2.Q + (int64_t)e3 * P) * 3 * TT;     // c of the layer's first plane
     for (int i = tid; i < P * TT; i += NT) {
         const int xx = i % T, yy = (i / T) % T, g3 = i / TT;
-        const int l1 = xx / P, h1 = xx % P;
-        const int e1 = min(e1b + l1, d0.K - 1);
-        const double *B1 = d0.B + ((int64_t)e1 * P + h1) * P, *D1 = d0.D + ((int64_t)e1 * P + h1) * P;
+        const int l1 = xx / P;
+        const double *B1 = t1B + xx * P, *D1 = t1D + xx * P;     // (l1 P + h1) P = xx P
         const double *r = sb + (g3 * T + yy) * NF + l1;
         double u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
@@ -108,48 +129,31 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(PatchView pv, const d
             u2 += B1[s] * r[SB + s];
             u3 += B1[s] * r[2 * SB + s];
         }
-        // points outside the patch have c = 0
-        const double *c = cv + cb0 + (int64_t)g3 * 3 * TT + yy * T + xx;
-        h[hb + i] = c[0] * u1 + c[TT] * u2 + c[2 * TT] * u3;
+        const double *c = cl + (int64_t)g3 * 3 * TT + yy * T + xx;
+        hs[i] = c[0] * u1 + c[TT] * u2 + c[2 * TT] * u3;
     }
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void conv_backward_kernel(PatchView pv, const double *__restrict__ h,
-                                                            double *__restrict__ y)
-{
-    using CT = ConvTile<P>;
-    constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, NFF = NF * NF, TT = T * T;
-    __shared__ double hs[P * TT];            // the tile's point values: [g3][yy][xx]
-    __shared__ double r1[P * T * NF];        // direction-1 sums: [g3][yy][lx]
-    __shared__ double r2[P * NFF];           // direction-2 sums: [g3][ly][lx]
-    const Dir &d0 = pv.dir[0], &d1 = pv.dir[1], &d2 = pv.dir[2];
-    const int bx = blockIdx.x, by = blockIdx.y, e3 = blockIdx.z;
-    const int e1b = bx * E, e2b = by * E;
-    const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
-    const int tid = threadIdx.x;
-    const int64_t tile = (int64_t)by * gridDim.x + bx;
-    const double *hb = h + (tile * d2.Q + (int64_t)e3 * P) * TT;
-    for (int i = tid; i < P * TT; i += NT) hs[i] = hb[i];
     __syncthreads();
-    // direction 1: function column lx gets sum over the elements l1 that
-    // activate it (local function j = lx - l1) and their points h1
-    for (int i = tid; i < P * T * NF; i += NT) {
-        const int lx = i % NF, row = i / NF;                 // row = g3 * T + yy
+    // ---- backward, direction 1: function column lx gets the sum over the
+    // elements l1 that activate it (local function j = lx - l1) and their
+    // points h1
+    double *r1 = sb;
+    for (int i = tid; i < SB; i += NT) {
+        const int lx = i % NF, row = i / NF;                  // row = g3 T + yy
         const double *hr = hs + row * T;
         double acc = 0.0;
 #pragma unroll
         for (int l1 = 0; l1 < E; ++l1) {
             const int j = lx - l1;
             if (j < 0 || j >= P) continue;
-            const double *B1 = d0.B + (int64_t)min(e1b + l1, d0.K - 1) * P * P + j;   // [h1][j], stride P
+            const double *B1 = t1B + l1 * PP + j;             // [h1][j], stride P
 #pragma unroll
             for (int h1 = 0; h1 < P; ++h1) acc += B1[h1 * P] * hr[l1 * P + h1];
         }
         r1[i] = acc;
     }
     __syncthreads();
-    // direction 2: function row ly, the same over l2 and h2
+    // ---- direction 2: function row ly, the same over l2 and h2
+    double *r2 = sa;
     for (int i = tid; i < P * NFF; i += NT) {
         const int lx = i % NF, ly = (i / NF) % NF, g3 = i / NFF;
         double acc = 0.0;
@@ -157,51 +161,49 @@ __global__ __launch_bounds__(256) void conv_backward_kernel(PatchView pv, const 
         for (int l2 = 0; l2 < E; ++l2) {
             const int j = ly - l2;
             if (j < 0 || j >= P) continue;
-            const double *B2 = d1.B + (int64_t)min(e2b + l2, d1.K - 1) * P * P + j;
+            const double *B2 = t2B + l2 * PP + j;
 #pragma unroll
             for (int h2 = 0; h2 < P; ++h2) acc += B2[h2 * P] * r1[(g3 * T + l2 * P + h2) * NF + lx];
         }
         r2[i] = acc;
     }
     __syncthreads();
-    // direction 3: function layer e3 + s, into y
-    const double *B3 = d2.B + (int64_t)e3 * P * P;
+    // ---- direction 3: function layer e3 + s, into y
     for (int i = tid; i < P * NFF; i += NT) {
         const int s = i / NFF, j = i % NFF;
         const int n0 = e1b + j % NF, n1 = e2b + j / NF;
         double acc = 0.0;
 #pragma unroll
-        for (int g3 = 0; g3 < P; ++g3) acc += B3[g3 * P + s] * r2[g3 * NFF + j];
+        for (int g3 = 0; g3 < P; ++g3) acc += t3B[g3 * P + s] * r2[g3 * NFF + j];
         if (n0 < d0.N && n1 < d1.N) atomicAdd(&y[n0 + N0 * n1 + N01 * (e3 + s)], acc);
     }
 }
 
 template <int P>
-static hipError_t launch_conv_p(const PatchView &pv, const double *cv, double *h, const double *x, double *y,
-                                hipStream_t s)
+static hipError_t launch_conv_p(const PatchView &pv, const double *cv, const double *x, double *y, hipStream_t s)
 {
-    constexpr int E = ConvTile<P>::E;
-    const dim3 grid((pv.dir[0].K + E - 1) / E, (pv.dir[1].K + E - 1) / E, pv.dir[2].K);
-    hipError_t e = launch_fill(y, pv.N, 0.0, s);
+    using CT = ConvTile<P>;
+    const size_t lds = sizeof(double) * CT::LDS;
+    hipError_t e = allow_dynamic_lds((const void *)conv_kernel<P>, lds);
+    if (e == hipSuccess) e = launch_fill(y, pv.N, 0.0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(conv_forward_kernel<P>, grid, dim3(ConvTile<P>::NT), 0, s, pv, cv, x, h);
-    hipLaunchKernelGGL(conv_backward_kernel<P>, grid, dim3(ConvTile<P>::NT), 0, s, pv, (const double *)h, y);
+    const dim3 grid((pv.dir[0].K + CT::E - 1) / CT::E, (pv.dir[1].K + CT::E - 1) / CT::E, pv.dir[2].K);
+    hipLaunchKernelGGL(conv_kernel<P>, grid, dim3(CT::NT), lds, s, pv, cv, x, y);
     return hipGetLastError();
 }
 
-hipError_t launch_conv_apply(const PatchView &pv, const double *cv, double *h, const double *x, double *y,
-                             hipStream_t s)
+hipError_t launch_conv_apply(const PatchView &pv, const double *cv, const double *x, double *y, hipStream_t s)
 {
     if (pv.d != 3) return hipErrorInvalidValue;
     switch (pv.P) {
-    case 2: return launch_conv_p<2>(pv, cv, h, x, y, s);
-    case 3: return launch_conv_p<3>(pv, cv, h, x, y, s);
-    case 4: return launch_conv_p<4>(pv, cv, h, x, y, s);
-    case 5: return launch_conv_p<5>(pv, cv, h, x, y, s);
-    case 6: return launch_conv_p<6>(pv, cv, h, x, y, s);
-    case 7: return launch_conv_p<7>(pv, cv, h, x, y, s);
-    case 8: return launch_conv_p<8>(pv, cv, h, x, y, s);
-    case 9: return launch_conv_p<9>(pv, cv, h, x, y, s);
+    case 2: return launch_conv_p<2>(pv, cv, x, y, s);
+    case 3: return launch_conv_p<3>(pv, cv, x, y, s);
+    case 4: return launch_conv_p<4>(pv, cv, x, y, s);
+    case 5: return launch_conv_p<5>(pv, cv, x, y, s);
+    case 6: return launch_conv_p<6>(pv, cv, x, y, s);
+    case 7: return launch_conv_p<7>(pv, cv, x, y, s);
+    case 8: return launch_conv_p<8>(pv, cv, x, y, s);
+    case 9: return launch_conv_p<9>(pv, cv, x, y, s);
     default: return hipErrorInvalidValue;
     }
 }

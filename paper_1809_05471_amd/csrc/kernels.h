@@ -72,18 +72,28 @@ __host__ __device__ inline int64_t apply_coef_size(int ncomp, int P, int K0, int
     return gx * gy * (int64_t)K2 * P * ncomp * T * T;
 }
 
-// Convection coefficient layout (d = 3): the tiles of apply_coef_index, per
-// tile and quadrature plane q3 the three components one after another, each
-// the tile's T x T columns (row ty, column tx).  The point buffer between the
-// two convection kernels is the same with one component (apply_coef_index
-// with ncomp = 1).  Columns outside the patch hold 0.
+// Elements per tile side of the convection kernel (d = 3): about 16
+// quadrature points per side up to order 6, two elements at orders 7 and 8
+// and one at order 9, so that its LDS stays near 64 KiB.
+__host__ __device__ constexpr int conv_tile_elems(int P) { return P <= 6 ? (16 + P - 1) / P : (P < 9 ? 2 : 1); }
+
+// Convection coefficient layout (d = 3): tiles of T x T quadrature columns
+// (T = conv_tile_elems(P) * P; direction 1 fastest), per tile and quadrature
+// plane q3 the three components one after another, each the tile's columns
+// (row ty, column tx).  Columns outside the patch hold 0.
 __host__ __device__ inline int64_t conv_coef_index(int comp, int q0, int q1, int q2, int P, int K0, int Q2)
 {
-    const int T = apply_tile_elems(P) * P;
+    const int T = conv_tile_elems(P) * P;
     const int gx = (K0 * P + T - 1) / T;
     const int bx = q0 / T, by = q1 / T;
     const int64_t tile = (int64_t)by * gx + bx;
     return ((tile * Q2 + q2) * 3 + comp) * (T * T) + (int64_t)(q1 - by * T) * T + (q0 - bx * T);
+}
+__host__ __device__ inline int64_t conv_coef_size(int P, int K0, int K1, int K2)
+{
+    const int T = conv_tile_elems(P) * P;
+    const int64_t gx = (K0 * P + T - 1) / T, gy = (K1 * P + T - 1) / T;
+    return gx * gy * (int64_t)K2 * P * 3 * T * T;
 }
 
 struct PatchView {
@@ -199,10 +209,8 @@ hipError_t launch_apply(const PatchView &pv, int op, Prec prec, const void *c, c
 // in the tiled layout (the geometry step then writes that copy as well)
 bool apply_tiled_layout(int P, int op, Prec prec);
 // Convection product y = B x (d = 3, FP64): cv the folded coefficients
-// (conv_coef_index layout), h a point buffer of apply_coef_size(1, ...)
-// doubles; y is overwritten.
-hipError_t launch_conv_apply(const PatchView &pv, const double *cv, double *h, const double *x, double *y,
-                             hipStream_t s);
+// (conv_coef_index layout); y is overwritten.
+hipError_t launch_conv_apply(const PatchView &pv, const double *cv, const double *x, double *y, hipStream_t s);
 // F16S storage from the FP32 coefficient tensor c32 of op (d = 3): per element
 // and component the reference r = (max + min) / 2 and scale s = (max - min) / 2
 // of C / w over the element's points (rs [K3][K2][K1][ncomp][2]), and per point

@@ -50,10 +50,10 @@ struct sf_patch {
     bool assembly_only = false;          // the relabelled copy of a patch: no apply
     // convection form (d = 3, FP64, matrix-free apply only): scalar
     // coefficient s and vector b, folded coefficients w s |det J| J^-1 b
-    // (conv_coef_index layout) and the point buffer between its two kernels
+    // (conv_coef_index layout)
     Coef coef_conv{0, 1.0, nullptr};
     double bconv[3] = {0.0, 0.0, 0.0};
-    double *Cv = nullptr, *hconv = nullptr;
+    double *Cv = nullptr;
     bool conv_ready = false;
     bool ready[2][4] = {};               // [op][precision mode]
     // level-2 workspace of the d = 3 assembly, sized once for the largest
@@ -184,7 +184,6 @@ void free_patch_memory(sf_patch *p)
         for (void *c : a) (void)hipFree(c);
     for (float *r : p->rs) (void)hipFree(r);
     (void)hipFree(p->Cv);
-    (void)hipFree(p->hconv);
 }
 
 }  // namespace
@@ -494,8 +493,8 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     if (ops & SF_CONV) {
         if (!p->Cv) {
             // columns outside the patch are never written: cleared once here
-            const size_t bytes = 3 * sizeof(double) * (size_t)apply_coef_size(1, p->P, p->view.dir[0].K,
-                                                                              p->view.dir[1].K, p->view.dir[2].K);
+            const size_t bytes = sizeof(double) * (size_t)conv_coef_size(p->P, p->view.dir[0].K, p->view.dir[1].K,
+                                                                         p->view.dir[2].K);
             sf_status st = alloc((void **)&p->Cv, bytes);
             if (st != SF_OK) return st;
             hipError_t e0 = hipMemsetAsync(p->Cv, 0, bytes, s);
@@ -870,17 +869,8 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
             return fail(p->ctx, SF_EINVAL, "operator not prepared at this precision (call sf_patch_prepare)");
         if (!x || !y) return fail(p->ctx, SF_EINVAL, "null vector");
         if (x == y) return fail(p->ctx, SF_EINVAL, "x and y must not overlap");
-        if (!p->hconv) {
-            const size_t bytes = sizeof(double) * (size_t)apply_coef_size(1, p->P, p->view.dir[0].K,
-                                                                          p->view.dir[1].K, p->view.dir[2].K);
-            hipError_t e = hipMalloc((void **)&p->hconv, bytes);
-            if (e != hipSuccess) {
-                p->hconv = nullptr;
-                return hip_fail(p->ctx, e, "convection point buffer");
-            }
-        }
-        hipError_t e = launch_conv_apply(p->view, p->Cv, p->hconv, x, y, p->ctx->stream);
-        if (e != hipSuccess) return hip_fail(p->ctx, e, "convection kernels");
+        hipError_t e = launch_conv_apply(p->view, p->Cv, x, y, p->ctx->stream);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "convection kernel");
         return SF_OK;
     }
     if (op != SF_MASS && op != SF_STIFF) return fail(p->ctx, SF_EINVAL, "op must be SF_MASS, SF_STIFF or SF_CONV");
