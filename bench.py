@@ -118,11 +118,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched", "order"], default="large",
+    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched", "order", "conv"], default="large",
                     help="large: d=3 128^3 order 6, geometry + pattern + assembly + 100 applies per step (the "
                          "headline line); single: 48^3 order 4 with one apply; sweep: matrix-free apply at "
                          "N = 126^3 for orders 2..9; batched: 512 patches; order: stiffness assembly of "
-                         "anisotropic patches in the given and the relabelled contraction order")
+                         "anisotropic patches in the given and the relabelled contraction order; conv: "
+                         "matrix-free convection product (FP64) at 128^3 order 6 and N = 126^3 for orders 2..9")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="precision of the timed step (default fp64; sweep and batched: see their help)")
     ap.add_argument("--mixed-steps", type=int, default=3,
@@ -157,6 +158,8 @@ def main():
         return run_batched(args)
     if args.workload == "order":
         return run_order(args)
+    if args.workload == "conv":
+        return run_conv(args)
     return run_patch(args)
 
 
@@ -454,6 +457,64 @@ def run_sweep(args):
                              "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                              "algorithmic_bytes": byts, "algorithmic_flops": apply_flops(K, p, "stiff")}}),
                 flush=True)
+        sf.sf_patch_destroy(h)
+        del x, y
+        torch.cuda.empty_cache()
+    sf.sf_ctx_destroy(ctx)
+
+
+def run_conv(args):
+    """Matrix-free convection product (b . grad u, FP64), d = 3: 128^3 order 6
+    (with err_y on sampled rows against the oracle unless --no-cpu-baseline)
+    and K = 127 - p per direction for orders 2..9; one JSON line each.
+    Algorithmic bytes: the three folded coefficients per point, x read and y
+    written once."""
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    stream = torch.cuda.current_stream()
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    b, alpha = (0.6, -0.9, 1.1), 0.5
+    cases = [((128, 128, 128), 6, inputs.workload_3d((128, 128, 128), 6))]
+    cases += [(w["K"], p, w) for p, w in ((p, inputs.workload_order_sweep(p)) for p in range(2, 10))]
+    for K, p, w in cases:
+        h = sf.sf_patch_create(ctx, 3, p, w["knots"], w["ctrl"])
+        N, nnz, Q = sf.sf_patch_info(h)
+        sf.sf_patch_set_coef(ctx, h, sf.SF_CONV, sf.SF_COEF_SINPROD, alpha)
+        sf.sf_patch_set_convection(ctx, h, b)
+        sf.sf_patch_prepare(ctx, h, sf.SF_CONV, sf.SF_FP64)
+        x = torch.as_tensor(w["x"]).cuda()
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            sf.sf_apply(ctx, h, sf.SF_CONV, sf.SF_FP64, x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            sf.sf_apply(ctx, h, sf.SF_CONV, sf.SF_FP64, x, y)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        byts = 24 * Q + 16 * N
+        line = {
+            "metric": "matrix-free apply GDoF/s", "value": N / (ms * 1e-3) / 1e9, "unit": "GDoF/s", "ms": ms,
+            "dtype": "f64", "config": {"workload": f"d3_{K[0]}^3_p{p}_convection_apply", "order": p, "ndof": N,
+                                       "nquad": Q},
+            "roofline": {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                         "traffic": (measured_traffic("traffic_conv_d3_128_p6_fp64.txt", ["conv.hip"])
+                                     if K[0] == 128 else None),
+                         "algorithmic_bytes": byts}}
+        if K[0] == 128 and not args.no_cpu_baseline:
+            import oracle
+            P = oracle.Problem(w["knots"], p, w["ctrl"], ("sinprod", alpha), conv_b=b)
+            rows = _sample_rows(P, p, [])
+            xh = np.asarray(w["x"], dtype=np.float64)
+            yref = P.apply_rows_by_elements(oracle.CONV, xh, rows)
+            den = max(float(np.abs(v) @ np.abs(xh[c])) for c, v in P.rows(oracle.CONV, rows))
+            line["err_y"] = float(np.abs(y.cpu().numpy()[rows] - yref).max() / den)
+            line["err_rows"] = int(len(rows))
+        print(json.dumps(line), flush=True)
         sf.sf_patch_destroy(h)
         del x, y
         torch.cuda.empty_cache()

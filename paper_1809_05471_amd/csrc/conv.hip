@@ -35,6 +35,7 @@ struct ConvTile {
     static constexpr int NT = 256;
     static constexpr int PP = P * P, NFF = NF * NF, TT = T * T;
     static constexpr int SB = P * T * NF;    // one field of the direction-2 results
+    static constexpr int NPT = (P * TT + NT - 1) / NT;   // points per thread
     // LDS in doubles: tables, x rows, direction-3 results, direction-2 results, point values
     static constexpr int LDS = 4 * E * PP + 2 * PP + P * NFF + 2 * P * NFF + 3 * SB + P * TT;
 };
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
 {
     using CT = ConvTile<P>;
     constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, PP = CT::PP, NFF = CT::NFF, TT = CT::TT;
-    constexpr int SB = CT::SB;
+    constexpr int SB = CT::SB, NPT = CT::NPT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *t1B = reinterpret_cast<double *>(smem_raw);   // [element l][point h][function j]
     double *t1D = t1B + E * PP, *t2B = t1D + E * PP, *t2D = t2B + E * PP;
@@ -60,6 +61,21 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     const int64_t N0 = d0.N, N01 = (int64_t)d0.N * d1.N;
     const int tid = threadIdx.x;
 
+    // The layer's coefficients of the thread's points are loaded first, into
+    // registers, and arrive while the forward stages run (the last thread's
+    // surplus points re-read the layer's last point and are not used).
+    const int64_t tile = (int64_t)by * gridDim.x + bx;
+    const double *cl = cv + (tile * d2.Q + (int64_t)e3 * P) * 3 * TT;     // c of the layer's first plane
+    double cr[NPT][3];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int i = min(tid + k * NT, P * TT - 1);
+        const int xx = i % T, yy = (i / T) % T, g3 = i / TT;
+        const double *c = cl + (int64_t)g3 * 3 * TT + yy * T + xx;
+        cr[k][0] = c[0];
+        cr[k][1] = c[TT];
+        cr[k][2] = c[2 * TT];
+    }
     // element tables (elements past the patch edge take the last element's:
     // their points have c = 0 and their functions are not stored)
     for (int i = tid; i < E * PP; i += NT) {
@@ -115,9 +131,10 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     }
     __syncthreads();
     // ---- direction 1 and the pointwise product, per point (g3, yy, xx)
-    const int64_t tile = (int64_t)by * gridDim.x + bx;
-    const double *cl = cv + (tile * d2.Q + (int64_t)e3 * P) * 3 * TT;     // c of the layer's first plane
-    for (int i = tid; i < P * TT; i += NT) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int i = tid + k * NT;
+        if (i >= P * TT) break;
         const int xx = i % T, yy = (i / T) % T, g3 = i / TT;
         const int l1 = xx / P;
         const double *B1 = t1B + xx * P, *D1 = t1D + xx * P;     // (l1 P + h1) P = xx P
@@ -129,8 +146,7 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
             u2 += B1[s] * r[SB + s];
             u3 += B1[s] * r[2 * SB + s];
         }
-        const double *c = cl + (int64_t)g3 * 3 * TT + yy * T + xx;
-        hs[i] = c[0] * u1 + c[TT] * u2 + c[2 * TT] * u3;
+        hs[i] = cr[k][0] * u1 + cr[k][1] * u2 + cr[k][2] * u3;
     }
     __syncthreads();
     // ---- backward, direction 1: function column lx gets the sum over the
