@@ -27,6 +27,11 @@
 
 namespace sfiga {
 
+// A table read by a whole wavefront at one address: through the constant
+// address space the compiler turns the reads into scalar loads.
+template <typename T>
+using conv_uniform_ptr = const __attribute__((address_space(4))) T *;
+
 template <int P>
 struct ConvTile {
     static constexpr int E = conv_tile_elems(P);
@@ -36,6 +41,20 @@ struct ConvTile {
     static constexpr int PP = P * P, NFF = NF * NF, TT = T * T;
     static constexpr int SB = P * T * NF;    // one field of the direction-2 results
     static constexpr int NPT = (P * TT + NT - 1) / NT;   // points per thread
+    // ROWF1: directions 2 and 1 (with the pointwise product) per element row
+    // (element, plane, function column or point row), the element uniform
+    // across a wavefront and its tables in scalar registers, rows padded to
+    // whole wavefronts per element: fewer LDS reads per multiply-add, but
+    // idle lanes and strided coefficient loads.  Measured per order at
+    // N = 126^3 against one item per point: 0.84 / 0.87 ms at order 4, 5.96 /
+    // 6.10 at 7, 21.9 / 24.8 at 9; slower at 2, 5, 6 and 8 (order 6: 4.11 /
+    // 3.06 ms, order 8: 13.0 / 10.6), equal at 3.
+    static constexpr bool ROWF1 = P == 4 || P == 7 || P == 9;
+    static constexpr int R = P * T, R64 = (R + 63) / 64 * 64;
+    static constexpr int NIT = (E * R64 + NT - 1) / NT;  // element rows per thread
+    // the same for direction 2 (element l2, plane g3, function column lx)
+    static constexpr int C2 = P * NF, C64 = (C2 + 63) / 64 * 64;
+    static constexpr int NIT2 = (E * C64 + NT - 1) / NT;
     // LDS in doubles: tables, x rows, direction-3 results, direction-2 results, point values
     static constexpr int LDS = 4 * E * PP + 2 * PP + P * NFF + 2 * P * NFF + 3 * SB + P * TT;
 };
@@ -47,6 +66,9 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     using CT = ConvTile<P>;
     constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, PP = CT::PP, NFF = CT::NFF, TT = CT::TT;
     constexpr int SB = CT::SB, NPT = CT::NPT;
+    constexpr bool ROWF1 = CT::ROWF1;
+    constexpr int R = CT::R, R64 = CT::R64, NIT = CT::NIT;
+    constexpr int C2 = CT::C2, C64 = CT::C64, NIT2 = CT::NIT2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *t1B = reinterpret_cast<double *>(smem_raw);   // [element l][point h][function j]
     double *t1D = t1B + E * PP, *t2B = t1D + E * PP, *t2D = t2B + E * PP;
@@ -66,15 +88,31 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     // surplus points re-read the layer's last point and are not used).
     const int64_t tile = (int64_t)by * gridDim.x + bx;
     const double *cl = cv + (tile * d2.Q + (int64_t)e3 * P) * 3 * TT;     // c of the layer's first plane
-    double cr[NPT][3];
+    double cr[ROWF1 ? 1 : NPT][3];
+    double crr[ROWF1 ? NIT : 1][3][ROWF1 ? P : 1];
+    if constexpr (ROWF1) {
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        const int i = min(tid + k * NT, P * TT - 1);
-        const int xx = i % T, yy = (i / T) % T, g3 = i / TT;
-        const double *c = cl + (int64_t)g3 * 3 * TT + yy * T + xx;
-        cr[k][0] = c[0];
-        cr[k][1] = c[TT];
-        cr[k][2] = c[2 * TT];
+        for (int k = 0; k < NIT; ++k) {
+            const int idx = min(tid + k * NT, E * R64 - 1);
+            const int l1 = idx / R64, r = min(idx % R64, R - 1);
+            const double *c = cl + (int64_t)(r / T) * 3 * TT + (r % T) * T + l1 * P;
+#pragma unroll
+            for (int h1 = 0; h1 < P; ++h1) {
+                crr[k][0][h1] = c[h1];
+                crr[k][1][h1] = c[TT + h1];
+                crr[k][2][h1] = c[2 * TT + h1];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = min(tid + k * NT, P * TT - 1);
+            const int xx = i % T, yy = (i / T) % T, g3 = i / TT;
+            const double *c = cl + (int64_t)g3 * 3 * TT + yy * T + xx;
+            cr[k][0] = c[0];
+            cr[k][1] = c[TT];
+            cr[k][2] = c[2 * TT];
+        }
     }
     // element tables (elements past the patch edge take the last element's:
     // their points have c = 0 and their functions are not stored)
@@ -111,8 +149,45 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
         sa[P * NFF + i] = b;
     }
     __syncthreads();
-    // ---- direction 2, per point row yy = (element l2, point h2): B2 a (for
-    // d1), D2 a (d2), B2 b (d3)
+    // ---- direction 2: B2 a (for d1), D2 a (d2), B2 b (d3) at the point rows
+    // yy = (element l2, point h2)
+    if constexpr (ROWF1) {
+        // per (element l2, plane, function column): the p values of a and b
+        // read once, the element's tables from scalar registers
+#pragma unroll
+        for (int k = 0; k < NIT2; ++k) {
+            const int idx = tid + k * NT;
+            if (idx >= E * C64) break;                        // whole wavefronts
+            const int l2 = __builtin_amdgcn_readfirstlane(idx / C64), c = idx % C64;
+            if (c < C2) {
+                const int g3 = c / NF, lx = c % NF;
+                const int e2 = min(e2b + l2, d1.K - 1);
+                const conv_uniform_ptr<double> B2 = (conv_uniform_ptr<double>)(d1.B + (int64_t)e2 * PP);
+                const conv_uniform_ptr<double> D2 = (conv_uniform_ptr<double>)(d1.D + (int64_t)e2 * PP);
+                const double *ca = sa + g3 * NFF + l2 * NF + lx, *cb = ca + P * NFF;
+                double va[P], vb[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    va[s] = ca[s * NF];
+                    vb[s] = cb[s * NF];
+                }
+                double *o = sb + (g3 * T + l2 * P) * NF + lx;
+#pragma unroll
+                for (int h2 = 0; h2 < P; ++h2) {
+                    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+                    for (int s = 0; s < P; ++s) {
+                        f0 += B2[h2 * P + s] * va[s];
+                        f1 += D2[h2 * P + s] * va[s];
+                        f2 += B2[h2 * P + s] * vb[s];
+                    }
+                    o[h2 * NF] = f0;
+                    o[SB + h2 * NF] = f1;
+                    o[2 * SB + h2 * NF] = f2;
+                }
+            }
+        }
+    } else {
     for (int i = tid; i < SB; i += NT) {
         const int lx = i % NF, yy = (i / NF) % T, g3 = i / (NF * T);
         const int l2 = yy / P;
@@ -129,8 +204,44 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
         sb[SB + i] = f1;
         sb[2 * SB + i] = f2;
     }
+    }
     __syncthreads();
-    // ---- direction 1 and the pointwise product, per point (g3, yy, xx)
+    // ---- direction 1 and the pointwise product
+    if constexpr (ROWF1) {
+        // per element row: the p direction-2 values of each field read once,
+        // the element's tables from scalar registers
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int idx = tid + k * NT;
+            if (idx >= E * R64) break;                        // whole wavefronts
+            const int l1 = __builtin_amdgcn_readfirstlane(idx / R64), r = idx % R64;
+            if (r < R) {
+                const int e1 = min(e1b + l1, d0.K - 1);
+                const conv_uniform_ptr<double> B1 = (conv_uniform_ptr<double>)(d0.B + (int64_t)e1 * PP);
+                const conv_uniform_ptr<double> D1 = (conv_uniform_ptr<double>)(d0.D + (int64_t)e1 * PP);
+                const double *rw = sb + r * NF + l1;          // r = g3 T + yy
+                double v0[P], v1[P], v2[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    v0[s] = rw[s];
+                    v1[s] = rw[SB + s];
+                    v2[s] = rw[2 * SB + s];
+                }
+                double *ho = hs + r * T + l1 * P;
+#pragma unroll
+                for (int h1 = 0; h1 < P; ++h1) {
+                    double u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+                    for (int s = 0; s < P; ++s) {
+                        u1 += D1[h1 * P + s] * v0[s];
+                        u2 += B1[h1 * P + s] * v1[s];
+                        u3 += B1[h1 * P + s] * v2[s];
+                    }
+                    ho[h1] = crr[k][0][h1] * u1 + crr[k][1][h1] * u2 + crr[k][2][h1] * u3;
+                }
+            }
+        }
+    } else {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int i = tid + k * NT;
@@ -147,6 +258,7 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
             u3 += B1[s] * r[2 * SB + s];
         }
         hs[i] = cr[k][0] * u1 + cr[k][1] * u2 + cr[k][2] * u3;
+    }
     }
     __syncthreads();
     // ---- backward, direction 1: function column lx gets the sum over the
