@@ -392,6 +392,81 @@ class Problem:
         return A
 
 
+def glue_map(d, nfuns, interfaces):
+    """Global numbering of conforming patches glued at faces (Sec. 4,
+    Example "Multipatch domains": the functions of two patches that meet on
+    an interface are identified, and the glued operator is
+    sum_b R_b^T A_b R_b).  nfuns[b][k]: functions of patch b in direction k;
+    interfaces: (patch a, face fa, patch b, face fb) with face = 2 k + side
+    (side 0 the functions with index 0 in direction k, side 1 the last);
+    the remaining directions, in increasing order, are matched index by index.
+    Returns (per patch an int64 array of global ids in the patch's
+    lexicographic order, the number of global functions).  Plain
+    union-find, for the small patches of the tests."""
+    offs = [0]
+    for nf in nfuns:
+        offs.append(offs[-1] + int(np.prod(nf[:d])))
+    parent = list(range(offs[-1]))
+
+    def find(i):
+        while parent[i] != i:
+            parent[i] = parent[parent[i]]
+            i = parent[i]
+        return i
+
+    def lin(nf, idx):
+        m, stride = 0, 1
+        for k in range(d):
+            m += idx[k] * stride
+            stride *= nf[k]
+        return m
+
+    for a, fa, b, fb in interfaces:
+        ka, sa_, kb, sb_ = fa // 2, fa % 2, fb // 2, fb % 2
+        ta = [k for k in range(d) if k != ka]
+        tb = [k for k in range(d) if k != kb]
+        na, nb = nfuns[a], nfuns[b]
+        if [na[k] for k in ta] != [nb[k] for k in tb]:
+            raise OracleError("non-conforming interface")
+        for t in np.ndindex(*[na[k] for k in ta]):
+            ia, ib = [0] * d, [0] * d
+            ia[ka] = na[ka] - 1 if sa_ else 0
+            ib[kb] = nb[kb] - 1 if sb_ else 0
+            for j in range(d - 1):
+                ia[ta[j]] = t[j]
+                ib[tb[j]] = t[j]
+            ra, rb = find(offs[a] + lin(na, ia)), find(offs[b] + lin(nb, ib))
+            if ra != rb:
+                parent[max(ra, rb)] = min(ra, rb)
+    gid = {}
+    out = []
+    for bi in range(len(nfuns)):
+        m = np.zeros(offs[bi + 1] - offs[bi], dtype=np.int64)
+        for i in range(len(m)):
+            r = find(offs[bi] + i)
+            if r not in gid:
+                gid[r] = len(gid)
+            m[i] = gid[r]
+        out.append(m)
+    return out, len(gid)
+
+
+def glued_apply(problems, maps, n_global, op, x, threads=0):
+    """y = sum_b R_b^T A_b R_b x over glued patches (see glue_map)."""
+    y = np.zeros(n_global)
+    for P, m in zip(problems, maps):
+        np.add.at(y, m, P.apply(op, np.asarray(x)[m], threads))
+    return y
+
+
+def glued_dense(problems, maps, n_global, op, threads=0):
+    """The glued matrix sum_b R_b^T A_b R_b, dense."""
+    A = np.zeros((n_global, n_global))
+    for P, m in zip(problems, maps):
+        A[np.ix_(m, m)] += P.dense(op, threads)
+    return A
+
+
 def csr_to_dense(rp, ci, v, n):
     A = np.zeros((n, n))
     for m in range(n):
