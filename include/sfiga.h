@@ -309,6 +309,32 @@ sf_status sf_batch_assemble(sf_batch *batch, unsigned ops, sf_precision prec, in
 sf_status sf_batch_apply(sf_batch *batch, unsigned op, sf_precision prec, const double *dev_x,
                          double *dev_y);
 
+/* Glued multipatch (Sec. 4, Example "Multipatch domains"): conforming
+ * patches identified at faces.  Host only, no context.  nfun [npatch][3]
+ * (host) holds the functions per direction of each patch (entries k >= d
+ * ignored); iface [ninterface][4] (host) the interfaces (patch a, face fa,
+ * patch b, face fb) with face = 2 k + side for direction k+1 (side 0: the
+ * functions with index 0 in that direction, side 1: the last); the other
+ * directions, in increasing order, must have equal function counts on both
+ * sides and are matched index by index (no flips or rotations).  Writes
+ * map [sum of the patches' N] (host): the global id of every patch-local
+ * function (patches in order, each lexicographic), ids numbered in order of
+ * first appearance, and *n_global.  SF_EINVAL for bad arguments or a
+ * non-conforming interface. */
+sf_status sf_glue_map(int d, int npatch, const int32_t *nfun, int ninterface, const int32_t *iface, int64_t *map,
+                      int64_t *n_global);
+
+/* y = sum_b R_b^T A_b R_b x (Sec. 4, Example "Multipatch domains"): the
+ * glued operator of the batch's patches under dev_map (device, [sum N]
+ * int64, e.g. sf_glue_map's map copied to the device; entries must lie in
+ * [0, n_global)); dev_x, dev_y device [n_global] FP64, y overwritten, no
+ * overlap.  Gathers the patch-local vectors, runs sf_batch_apply on them
+ * and adds back with FP64 atomics (the last bits may vary between runs).
+ * The patch-local vectors (2 x sum N doubles) are allocated by the first
+ * call and kept with the batch.  Preparation and errors as sf_batch_apply. */
+sf_status sf_batch_apply_glued(sf_batch *batch, unsigned op, sf_precision prec, const int64_t *dev_map,
+                               int64_t n_global, const double *dev_x, double *dev_y);
+
 void sf_batch_destroy(sf_batch *batch);
 
 #ifdef __cplusplus

@@ -29,7 +29,8 @@ EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target
             "sf_patch_create",
             "sf_patch_info", "sf_patch_set_coef", "sf_patch_set_convection", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
             "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_assemble_noalloc", "sf_apply", "sf_patch_destroy", "sf_batch_create",
-            "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_batch_destroy"]
+            "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_glue_map", "sf_batch_apply_glued",
+            "sf_batch_destroy"]
 
 
 class SfError(RuntimeError):
@@ -76,6 +77,8 @@ def lib():
         "sf_batch_offsets": (st, [vp, i64p, i64p]),
         "sf_batch_assemble": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp, vp, vp]),
         "sf_batch_apply": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, vp]),
+        "sf_glue_map": (st, [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, vp, i64p]),
+        "sf_batch_apply_glued": (st, [vp, ctypes.c_uint, ctypes.c_int, vp, ctypes.c_int64, vp, vp]),
         "sf_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -252,6 +255,27 @@ def sf_batch_assemble(ctx, batch, ops, prec, row_ptr, col_ind, val_mass=None, va
 
 def sf_batch_apply(ctx, batch, op, prec, x, y):
     _check(lib().sf_batch_apply(batch, op, prec, _ptr(x), _ptr(y)), ctx)
+
+
+def sf_glue_map(d, nfuns, interfaces):
+    """Host: nfuns [npatch][<=3] functions per direction, interfaces
+    [(patch a, face fa, patch b, face fb)]; returns (map int64 [sum N], n_global)."""
+    nf = np.zeros((len(nfuns), 3), dtype=np.int32)
+    for b, n in enumerate(nfuns):
+        nf[b, :len(n)] = n
+    ifc = np.ascontiguousarray(np.asarray(interfaces, dtype=np.int32).reshape(-1, 4))
+    total = int(sum(np.prod(n[:d]) for n in nfuns))
+    m = np.zeros(total, dtype=np.int64)
+    ng = ctypes.c_int64()
+    st = lib().sf_glue_map(d, len(nfuns), nf.ctypes.data, len(ifc), ifc.ctypes.data if len(ifc) else None,
+                           m.ctypes.data, ctypes.byref(ng))
+    if st != SF_OK:
+        raise SfError(st, "sf_glue_map")
+    return m, ng.value
+
+
+def sf_batch_apply_glued(ctx, batch, op, prec, dev_map, n_global, x, y):
+    _check(lib().sf_batch_apply_glued(batch, op, prec, _ptr(dev_map), int(n_global), _ptr(x), _ptr(y)), ctx)
 
 
 def sf_batch_destroy(batch):

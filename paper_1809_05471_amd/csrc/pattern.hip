@@ -218,6 +218,42 @@ hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s)
     return hipGetLastError();
 }
 
+// Glued multipatch (Sec. 4, Example "Multipatch domains"): patch-local
+// vectors from the global one and back, y = sum_b R_b^T (A_b R_b x).
+__global__ void glue_gather_kernel(const int64_t *__restrict__ map, int64_t n, const double *__restrict__ xg,
+                                   double *__restrict__ xl)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        xl[i] = xg[map[i]];
+}
+
+__global__ void glue_scatter_kernel(const int64_t *__restrict__ map, int64_t n, const double *__restrict__ yl,
+                                    double *__restrict__ yg)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&yg[map[i]], yl[i]);
+}
+
+static unsigned grid_of(int64_t n)
+{
+    const int64_t nb = (n + 255) / 256;
+    return (unsigned)(nb > 65536 ? 65536 : (nb < 1 ? 1 : nb));
+}
+
+hipError_t launch_glue_gather(const int64_t *map, int64_t n, const double *xg, double *xl, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(glue_gather_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, xg, xl);
+    return hipGetLastError();
+}
+
+hipError_t launch_glue_scatter(const int64_t *map, int64_t n, const double *yl, double *yg, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(glue_scatter_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, yl, yg);
+    return hipGetLastError();
+}
+
 hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_ind, int64_t row_base,
                           int64_t col_base, int64_t nnz_base, hipStream_t s)
 {

@@ -99,6 +99,8 @@ struct sf_batch {
     };
     std::vector<Tuned> tuned;
     std::vector<void *> dev;      // device task lists referenced by the graphs
+    // patch-local x and y of the glued apply (sum N each), allocated by its first call
+    double *xl = nullptr, *yl = nullptr;
 };
 
 namespace sfiga {
@@ -1304,7 +1306,113 @@ void sf_batch_destroy(sf_batch *b)
     (void)hipStreamSynchronize(b->ctx->stream);
     for (auto &c : b->graphs) (void)hipGraphExecDestroy(c.exec);
     for (void *m : b->dev) (void)hipFree(m);
+    (void)hipFree(b->xl);
+    (void)hipFree(b->yl);
     delete b;
+}
+
+sf_status sf_glue_map(int d, int npatch, const int32_t *nfun, int ninterface, const int32_t *iface, int64_t *map,
+                      int64_t *n_global)
+{
+    if (d < 1 || d > 3 || npatch < 1 || ninterface < 0 || !nfun || !map || !n_global || (ninterface > 0 && !iface))
+        return SF_EINVAL;
+    std::vector<int64_t> off(npatch + 1, 0);
+    for (int b = 0; b < npatch; ++b) {
+        int64_t n = 1;
+        for (int k = 0; k < d; ++k) {
+            if (nfun[3 * b + k] < 1) return SF_EINVAL;
+            n *= nfun[3 * b + k];
+        }
+        off[b + 1] = off[b] + n;
+    }
+    // union-find over the patch-local functions; roots are the smallest index
+    std::vector<int64_t> parent(off[npatch]);
+    for (int64_t i = 0; i < off[npatch]; ++i) parent[i] = i;
+    auto find = [&](int64_t i) {
+        int64_t r = i;
+        while (parent[r] != r) r = parent[r];
+        while (parent[i] != r) {
+            const int64_t n = parent[i];
+            parent[i] = r;
+            i = n;
+        }
+        return r;
+    };
+    auto lin = [&](int b, const int *idx) {
+        int64_t m = 0, stride = 1;
+        for (int k = 0; k < d; ++k) {
+            m += idx[k] * stride;
+            stride *= nfun[3 * b + k];
+        }
+        return off[b] + m;
+    };
+    for (int f = 0; f < ninterface; ++f) {
+        const int a = iface[4 * f], fa = iface[4 * f + 1], b = iface[4 * f + 2], fb = iface[4 * f + 3];
+        if (a < 0 || a >= npatch || b < 0 || b >= npatch || fa < 0 || fa >= 2 * d || fb < 0 || fb >= 2 * d)
+            return SF_EINVAL;
+        const int ka = fa / 2, kb = fb / 2;
+        int ta[2], tb[2], nt = 0;
+        for (int k = 0, ia = 0, ib = 0; k < d; ++k) {
+            if (k != ka) ta[ia++] = k;
+            if (k != kb) tb[ib++] = k;
+        }
+        nt = d - 1;
+        int cnt[2] = {1, 1};
+        for (int j = 0; j < nt; ++j) {
+            if (nfun[3 * a + ta[j]] != nfun[3 * b + tb[j]]) return SF_EINVAL;   // not conforming
+            cnt[j] = nfun[3 * a + ta[j]];
+        }
+        for (int t1 = 0; t1 < cnt[1]; ++t1)
+            for (int t0 = 0; t0 < cnt[0]; ++t0) {
+                int ia[3] = {0, 0, 0}, ib[3] = {0, 0, 0};
+                ia[ka] = fa % 2 ? nfun[3 * a + ka] - 1 : 0;
+                ib[kb] = fb % 2 ? nfun[3 * b + kb] - 1 : 0;
+                const int t[2] = {t0, t1};
+                for (int j = 0; j < nt; ++j) {
+                    ia[ta[j]] = t[j];
+                    ib[tb[j]] = t[j];
+                }
+                const int64_t ra = find(lin(a, ia)), rb = find(lin(b, ib));
+                if (ra != rb) parent[ra > rb ? ra : rb] = ra < rb ? ra : rb;
+            }
+    }
+    // global ids in the order of first appearance (patch order, lexicographic)
+    std::vector<int64_t> gid(off[npatch], -1);
+    int64_t next = 0;
+    for (int64_t i = 0; i < off[npatch]; ++i) {
+        const int64_t r = find(i);
+        if (gid[r] < 0) gid[r] = next++;
+        map[i] = gid[r];
+    }
+    *n_global = next;
+    return SF_OK;
+}
+
+sf_status sf_batch_apply_glued(sf_batch *b, unsigned op, sf_precision prec, const int64_t *dev_map, int64_t n_global,
+                               const double *x, double *y)
+{
+    if (!b) return SF_EINVAL;
+    sf_ctx *ctx = b->ctx;
+    ctx->err.clear();
+    if (!dev_map || !x || !y || x == y || n_global < 1) return fail(ctx, SF_EINVAL, "bad map or vectors");
+    const int64_t nloc = b->row_off.back();
+    hipStream_t s = ctx->stream;
+    for (double **v : {&b->xl, &b->yl})
+        if (!*v) {
+            hipError_t e = hipMalloc((void **)v, sizeof(double) * (size_t)nloc);
+            if (e != hipSuccess) {
+                *v = nullptr;
+                return hip_fail(ctx, e, "patch-local vectors of the glued apply");
+            }
+        }
+    hipError_t e = launch_glue_gather(dev_map, nloc, x, b->xl, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "glued gather");
+    sf_status st = sf_batch_apply(b, op, prec, b->xl, b->yl);
+    if (st != SF_OK) return st;
+    e = launch_fill(y, n_global, 0.0, s);
+    if (e == hipSuccess) e = launch_glue_scatter(dev_map, nloc, b->yl, y, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "glued scatter");
+    return SF_OK;
 }
 
 }  // extern "C"
