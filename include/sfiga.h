@@ -326,8 +326,9 @@ sf_status sf_glue_map(int d, int npatch, const int32_t *nfun, int ninterface, co
 
 /* y = sum_b R_b^T A_b R_b x (Sec. 4, Example "Multipatch domains"): the
  * glued operator of the batch's patches under dev_map (device, [sum N]
- * int64, e.g. sf_glue_map's map copied to the device; entries must lie in
- * [0, n_global)); dev_x, dev_y device [n_global] FP64, y overwritten, no
+ * int64, e.g. sf_glue_map's map copied to the device; an entry outside
+ * [0, n_global) is not followed: its local value is 0 and its result is
+ * dropped); dev_x, dev_y device [n_global] FP64, y overwritten, no
  * overlap.  Gathers the patch-local vectors, runs sf_batch_apply on them
  * and adds back with FP64 atomics (the last bits may vary between runs).
  * The patch-local vectors (2 x sum N doubles) are allocated by the first

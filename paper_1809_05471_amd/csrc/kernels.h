@@ -194,9 +194,10 @@ hipError_t launch_pattern(const PatchView &pv, int64_t *row_ptr, int32_t *col_in
                           int64_t col_base, int64_t nnz_base, hipStream_t s);
 hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s);
 // glued multipatch vectors: xl[i] = xg[map[i]] and yg[map[i]] += yl[i]
-// (FP64 atomics), i < n; map entries in [0, length of xg / yg)
-hipError_t launch_glue_gather(const int64_t *map, int64_t n, const double *xg, double *xl, hipStream_t s);
-hipError_t launch_glue_scatter(const int64_t *map, int64_t n, const double *yl, double *yg, hipStream_t s);
+// (FP64 atomics), i < n, for map entries in [0, ng) (the length of xg and
+// yg); other entries give xl[i] = 0 and add nothing
+hipError_t launch_glue_gather(const int64_t *map, int64_t n, int64_t ng, const double *xg, double *xl, hipStream_t s);
+hipError_t launch_glue_scatter(const int64_t *map, int64_t n, int64_t ng, const double *yl, double *yg, hipStream_t s);
 // Values assembled on `alt`, the d = 3 patch pv with its directions relabelled
 // cyclically (alt direction k = pv direction (k + sh) mod 3), moved into pv's
 // CSR layout (tmp: alt's values, vals: pv's).

@@ -220,18 +220,24 @@ hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s)
 
 // Glued multipatch (Sec. 4, Example "Multipatch domains"): patch-local
 // vectors from the global one and back, y = sum_b R_b^T (A_b R_b x).
-__global__ void glue_gather_kernel(const int64_t *__restrict__ map, int64_t n, const double *__restrict__ xg,
-                                   double *__restrict__ xl)
+// Map entries outside [0, ng) are not followed (the local value is 0, the
+// result is dropped).
+__global__ void glue_gather_kernel(const int64_t *__restrict__ map, int64_t n, int64_t ng,
+                                   const double *__restrict__ xg, double *__restrict__ xl)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        xl[i] = xg[map[i]];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = map[i];
+        xl[i] = (j >= 0 && j < ng) ? xg[j] : 0.0;
+    }
 }
 
-__global__ void glue_scatter_kernel(const int64_t *__restrict__ map, int64_t n, const double *__restrict__ yl,
-                                    double *__restrict__ yg)
+__global__ void glue_scatter_kernel(const int64_t *__restrict__ map, int64_t n, int64_t ng,
+                                    const double *__restrict__ yl, double *__restrict__ yg)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&yg[map[i]], yl[i]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = map[i];
+        if (j >= 0 && j < ng) atomicAdd(&yg[j], yl[i]);
+    }
 }
 
 static unsigned grid_of(int64_t n)
@@ -240,17 +246,17 @@ static unsigned grid_of(int64_t n)
     return (unsigned)(nb > 65536 ? 65536 : (nb < 1 ? 1 : nb));
 }
 
-hipError_t launch_glue_gather(const int64_t *map, int64_t n, const double *xg, double *xl, hipStream_t s)
+hipError_t launch_glue_gather(const int64_t *map, int64_t n, int64_t ng, const double *xg, double *xl, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(glue_gather_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, xg, xl);
+    hipLaunchKernelGGL(glue_gather_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, ng, xg, xl);
     return hipGetLastError();
 }
 
-hipError_t launch_glue_scatter(const int64_t *map, int64_t n, const double *yl, double *yg, hipStream_t s)
+hipError_t launch_glue_scatter(const int64_t *map, int64_t n, int64_t ng, const double *yl, double *yg, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(glue_scatter_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, yl, yg);
+    hipLaunchKernelGGL(glue_scatter_kernel, dim3(grid_of(n)), dim3(256), 0, s, map, n, ng, yl, yg);
     return hipGetLastError();
 }
 

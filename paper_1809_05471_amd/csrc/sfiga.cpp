@@ -1405,12 +1405,12 @@ sf_status sf_batch_apply_glued(sf_batch *b, unsigned op, sf_precision prec, cons
                 return hip_fail(ctx, e, "patch-local vectors of the glued apply");
             }
         }
-    hipError_t e = launch_glue_gather(dev_map, nloc, x, b->xl, s);
+    hipError_t e = launch_glue_gather(dev_map, nloc, n_global, x, b->xl, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "glued gather");
     sf_status st = sf_batch_apply(b, op, prec, b->xl, b->yl);
     if (st != SF_OK) return st;
     e = launch_fill(y, n_global, 0.0, s);
-    if (e == hipSuccess) e = launch_glue_scatter(dev_map, nloc, b->yl, y, s);
+    if (e == hipSuccess) e = launch_glue_scatter(dev_map, nloc, n_global, b->yl, y, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "glued scatter");
     return SF_OK;
 }
