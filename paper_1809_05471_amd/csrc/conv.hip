@@ -50,6 +50,13 @@ struct ConvTile {
     // 6.10 at 7, 21.9 / 24.8 at 9; slower at 2, 5, 6 and 8 (order 6: 4.11 /
     // 3.06 ms, order 8: 13.0 / 10.6), equal at 3.
     static constexpr bool ROWF1 = P == 4 || P == 7 || P == 9;
+    // ROWB: backward directions 1 and 2 per element row as well, each item
+    // adding its p sums into the shared rows with LDS atomics.  Measured at
+    // N = 126^3 against the gather per function: 0.110 / 0.126 ms at order 2,
+    // 0.41 / 0.43 at 3, 0.80 / 0.85 at 4, 3.07 / 3.10 at 6, 5.68 / 5.96 at 7,
+    // equal at 5; slower at 8 (10.84 / 10.74) and at 9, where it spills
+    // (26.4 / 22.0 ms).
+    static constexpr bool ROWB = P <= 7;
     static constexpr int R = P * T, R64 = (R + 63) / 64 * 64;
     static constexpr int NIT = (E * R64 + NT - 1) / NT;  // element rows per thread
     // the same for direction 2 (element l2, plane g3, function column lx)
@@ -66,7 +73,7 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     using CT = ConvTile<P>;
     constexpr int E = CT::E, T = CT::T, NF = CT::NF, NT = CT::NT, PP = CT::PP, NFF = CT::NFF, TT = CT::TT;
     constexpr int SB = CT::SB, NPT = CT::NPT;
-    constexpr bool ROWF1 = CT::ROWF1;
+    constexpr bool ROWF1 = CT::ROWF1, ROWB = CT::ROWB;
     constexpr int R = CT::R, R64 = CT::R64, NIT = CT::NIT;
     constexpr int C2 = CT::C2, C64 = CT::C64, NIT2 = CT::NIT2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -207,6 +214,12 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     }
     __syncthreads();
     // ---- direction 1 and the pointwise product
+    if constexpr (ROWB) {
+        // the backward direction-1 sums are added into the x / direction-3
+        // region (free from here on): cleared now
+        static_assert(SB <= 3 * P * NFF, "direction-1 sums fit in the x and direction-3 buffers");
+        for (int i = tid; i < SB; i += NT) xs[i] = 0.0;
+    }
     if constexpr (ROWF1) {
         // per element row: the p direction-2 values of each field read once,
         // the element's tables from scalar registers
@@ -264,7 +277,35 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
     // ---- backward, direction 1: function column lx gets the sum over the
     // elements l1 that activate it (local function j = lx - l1) and their
     // points h1
-    double *r1 = sb;
+    double *r1 = ROWB ? xs : sb;
+    double *r2 = ROWB ? sb : sa;
+    if constexpr (ROWB) {
+        // per element row (element l1, row g3 T + yy): its p point values read
+        // once, its p sums added into the row with LDS atomics (the elements
+        // that share a column meet there); the direction-2 sums' buffer (the
+        // direction-2 forward region, free now) cleared meanwhile
+        for (int i = tid; i < P * NFF; i += NT) r2[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int idx = tid + k * NT;
+            if (idx >= E * R64) break;                        // whole wavefronts
+            const int l1 = __builtin_amdgcn_readfirstlane(idx / R64), r = idx % R64;
+            if (r < R) {
+                const int e1 = min(e1b + l1, d0.K - 1);
+                const conv_uniform_ptr<double> B1 = (conv_uniform_ptr<double>)(d0.B + (int64_t)e1 * PP);
+                double v[P];
+#pragma unroll
+                for (int h1 = 0; h1 < P; ++h1) v[h1] = hs[r * T + l1 * P + h1];
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int h1 = 0; h1 < P; ++h1) acc += B1[h1 * P + j] * v[h1];
+                    atomicAdd(&r1[r * NF + l1 + j], acc);
+                }
+            }
+        }
+    } else {
     for (int i = tid; i < SB; i += NT) {
         const int lx = i % NF, row = i / NF;                  // row = g3 T + yy
         const double *hr = hs + row * T;
@@ -279,9 +320,33 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
         }
         r1[i] = acc;
     }
+    }
     __syncthreads();
     // ---- direction 2: function row ly, the same over l2 and h2
-    double *r2 = sa;
+    if constexpr (ROWB) {
+        // per (element l2, plane, function column), atomics as above
+#pragma unroll
+        for (int k = 0; k < NIT2; ++k) {
+            const int idx = tid + k * NT;
+            if (idx >= E * C64) break;                        // whole wavefronts
+            const int l2 = __builtin_amdgcn_readfirstlane(idx / C64), c = idx % C64;
+            if (c < C2) {
+                const int g3 = c / NF, lx = c % NF;
+                const int e2 = min(e2b + l2, d1.K - 1);
+                const conv_uniform_ptr<double> B2 = (conv_uniform_ptr<double>)(d1.B + (int64_t)e2 * PP);
+                double v[P];
+#pragma unroll
+                for (int h2 = 0; h2 < P; ++h2) v[h2] = r1[(g3 * T + l2 * P + h2) * NF + lx];
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int h2 = 0; h2 < P; ++h2) acc += B2[h2 * P + j] * v[h2];
+                    atomicAdd(&r2[g3 * NFF + (l2 + j) * NF + lx], acc);
+                }
+            }
+        }
+    } else {
     for (int i = tid; i < P * NFF; i += NT) {
         const int lx = i % NF, ly = (i / NF) % NF, g3 = i / NFF;
         double acc = 0.0;
@@ -294,6 +359,7 @@ __global__ __launch_bounds__(256) void conv_kernel(PatchView pv, const double *_
             for (int h2 = 0; h2 < P; ++h2) acc += B2[h2 * P] * r1[(g3 * T + l2 * P + h2) * NF + lx];
         }
         r2[i] = acc;
+    }
     }
     __syncthreads();
     // ---- direction 3: function layer e3 + s, into y
