@@ -170,3 +170,22 @@ def test_conv_error_paths():
         assert ei.value.status == sf.SF_EUNSUPPORTED
     finally:
         sf.sf_patch_destroy(h2)
+
+
+def test_conv_qp_values_coefficient_matches_builtin():
+    """SF_COEF_QPVALUES for the convection factor s, fed with the built-in
+    sinprod at sf_patch_quad_points, gives the built-in product."""
+    import torch
+    K, p = (5, 4, 3), 4
+    kn, ctrl = inputs.perturbed_geometry(K, p, seed=9, amp=0.1)
+    x = inputs.random_vector(int(np.prod([k + p - 1 for k in K])), 2)
+    with ConvPatch(kn, p, ctrl, ("sinprod", 0.5), (0.3, 1.0, -0.4)) as g:
+        g.prepare()
+        ref = g.apply(x)
+        xyz = torch.empty((g.Q, 3), dtype=torch.float64, device="cuda")
+        sf.sf_patch_quad_points(ctx(), g.h, xyz)
+        s = (1.0 + 0.5 * torch.prod(torch.sin(2 * np.pi * xyz), dim=1)).contiguous()
+        sf.sf_patch_set_coef(ctx(), g.h, sf.SF_CONV, sf.SF_COEF_QPVALUES, qp_values=s)
+        g.prepare()
+        y = g.apply(x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()

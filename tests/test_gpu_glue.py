@@ -98,3 +98,62 @@ def test_glued_apply_errors():
     finally:
         for g in patches:
             g.close()
+
+
+def test_two_glued_groups_of_different_orders_in_one_batch():
+    """Pieces of two C0 patches (orders 3 and 5) in one batch: the glued map
+    is block-diagonal between the groups and the persistent launches mix
+    the orders; each group against the oracle's C0 patch."""
+    import torch
+    c, stream = side_ctx()
+    groups = [((4, 4, 3), ((2, 2), (4,), (3,)), 3), ((4, 3, 4), ((2, 2), (3,), (1, 3)), 5)]
+    built, nf, ifc = [], [], []
+    for K, splits, p in groups:
+        kn0, ctrl0, pieces = c0_split(K, splits, p, seed=4)
+        base = len(nf)
+        ifc += [(a + base, fa, b + base, fb) for a, fa, b, fb in interfaces_of(splits)]
+        nf += [pc[2] for pc in pieces]
+        built.append((kn0, ctrl0, pieces, p))
+    m, ng = sf.sf_glue_map(3, nf, ifc)
+    offs = np.cumsum([0] + [int(np.prod(n)) for n in nf])
+    patches = []
+    with torch.cuda.stream(stream):
+        try:
+            for kn0, ctrl0, pieces, p in built:
+                for kn, cc, _, _ in pieces:
+                    g = GpuPatch(kn, p, cc, ("sinprod", 0.4), context=c)
+                    g.prepare()
+                    patches.append(g)
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            x = inputs.random_vector(ng, 8)
+            dmap = torch.as_tensor(m).cuda()
+            y = torch.empty(ng, dtype=torch.float64, device="cuda")
+            for rep in range(2):
+                y.fill_(float("nan"))
+                sf.sf_batch_apply_glued(c, bt, sf.SF_STIFF, sf.SF_FP64, dmap, ng, torch.as_tensor(x).cuda(), y)
+                stream.synchronize()
+                yn = y.cpu().numpy()
+                b = 0
+                for kn0, ctrl0, pieces, p in built:
+                    single = oracle.Problem(kn0, p, ctrl0, ("sinprod", 0.4))
+                    perm = {}
+                    for pc in pieces:
+                        for gid, c0 in zip(m[offs[b]:offs[b + 1]], pc[3]):
+                            perm[int(gid)] = int(c0)
+                        b += 1
+                    gids = np.array(sorted(perm))
+                    c0i = np.array([perm[i] for i in gids])
+                    assert len(gids) == single.N
+                    xc0 = np.zeros(single.N)
+                    xc0[c0i] = x[gids]
+                    yc0 = single.apply(oracle.STIFF, xc0)
+                    rp, ci, v = single.assemble(oracle.STIFF)
+                    absAx = np.array([np.abs(v[rp[r]:rp[r + 1]]) @ np.abs(xc0[ci[rp[r]:rp[r + 1]]])
+                                      for r in range(single.N)])
+                    e = err_y(yn[gids], yc0[c0i], absAx[c0i])
+                    record("err_y", sf.SF_FP64, e)
+                    assert e <= TOL[sf.SF_FP64], (rep, p, e)
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
