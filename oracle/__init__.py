@@ -81,6 +81,8 @@ def _lib():
     lib.orc_measure.argtypes = prob + [f64p]
     lib.orc_set_convection.argtypes = [ctypes.c_double] * 3
     lib.orc_set_convection.restype = None
+    lib.orc_set_diffusion.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    lib.orc_set_diffusion.restype = None
     for f in (lib.orc_pattern, lib.orc_assemble, lib.orc_rows, lib.orc_apply_rows,
               lib.orc_apply, lib.orc_apply_elements, lib.orc_eval, lib.orc_measure):
         f.restype = ctypes.c_int
@@ -212,11 +214,17 @@ class Problem:
     coefficient: ``("const", value)`` or ``("sinprod", alpha)`` meaning
     1 + alpha * prod_i sin(2 pi x_i) at the physical point.  The stiffness
     and convection forms take that coefficient, the mass form c = 1;
-    ``conv_b`` is the constant vector b of the convection form."""
+    ``conv_b`` is the constant vector b of the convection form and
+    ``diff_A`` the constant symmetric matrix A of the stiffness form
+    (diffusion a(x) A; default the identity)."""
 
-    def __init__(self, knots, orders, ctrl, coef=("const", 1.0), conv_b=(0.0, 0.0, 0.0)):
+    def __init__(self, knots, orders, ctrl, coef=("const", 1.0), conv_b=(0.0, 0.0, 0.0), diff_A=None):
         self.d = len(knots)
         self.conv_b = [float(v) for v in conv_b] + [0.0] * (3 - len(conv_b))
+        A = np.eye(3)
+        if diff_A is not None:
+            A[:self.d, :self.d] = np.asarray(diff_A, dtype=np.float64)
+        self.diff_A = np.ascontiguousarray(A.ravel())
         if isinstance(orders, int):
             orders = [orders] * self.d
         self.orders = list(orders)
@@ -243,6 +251,7 @@ class Problem:
         i32 = P(ctypes.c_int32)
         f64 = P(ctypes.c_double)
         _lib().orc_set_convection(*self.conv_b[:3])
+        _lib().orc_set_diffusion(self.diff_A.ctypes.data_as(f64))
         return [self.d, self._p.ctypes.data_as(i32), self._nel.ctypes.data_as(i32),
                 self._nf.ctypes.data_as(i32), self._first.ctypes.data_as(i32),
                 self._w.ctypes.data_as(f64), self._phi.ctypes.data_as(f64),

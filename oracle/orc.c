@@ -12,7 +12,8 @@
  *
  *   mass      M[m][n] = sum_x  w(x) c(G(x)) |det J(x)| phi_n(x) phi_m(x)
  *   stiffness K[m][n] = sum_x  w(x) a(G(x)) |det J(x)|
- *                             (J^-T grad phi_n)(x) . (J^-T grad phi_m)(x)
+ *                             (J^-T grad phi_n)(x) . A (J^-T grad phi_m)(x)
+ *             (A a constant symmetric matrix, orc_set_diffusion; default I)
  *   convection B[m][n] = sum_x w(x) s(G(x)) |det J(x)|
  *                             (b . J^-T grad phi_n)(x) phi_m(x)
  *
@@ -143,6 +144,24 @@ static int prob_init(prob_t *P, int d, const int *p, const int *nel, const int *
 static int orc_defect = 0;
 
 void orc_set_defect(int k) { orc_defect = k; }
+
+/* the constant symmetric diffusion matrix A of the stiffness form (op 2),
+ * row-major 3 x 3, its first d rows and columns used; default identity */
+static double orc_diff_A[MAXD][MAXD] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+void orc_set_diffusion(const double *A9)
+{
+    for (int i = 0; i < MAXD; ++i)
+        for (int j = 0; j < MAXD; ++j) orc_diff_A[i][j] = A9[3 * i + j];
+}
+
+/* g . A h over the first d components */
+static inline double diff_dot(const prob_t *P, const double *g, const double *h)
+{
+    double t = 0.0;
+    for (int i = 0; i < P->d; ++i)
+        for (int j = 0; j < P->d; ++j) t += g[i] * orc_diff_A[i][j] * h[j];
+    return t;
+}
 
 /* the constant vector b of the convection form (op 4) */
 static double orc_conv_b[MAXD] = {0.0, 0.0, 0.0};
@@ -405,7 +424,7 @@ int orc_assemble(PROB_ARGS, int op, const int64_t *row_ptr, double *vals, int nt
                                                 : conv_deriv(&P, Q->grad[b]) * Q->val[a];
                         } else {
                             t = 0.0;
-                            for (int i = 0; i < P.d; ++i) t += Q->grad[b][i] * Q->grad[a][i];
+                            t = diff_dot(&P, Q->grad[b], Q->grad[a]);
                         }
                         rowv[box_offset(&P, Q->lidx[a], Q->lidx[b])] += s * t;
                     }
@@ -491,7 +510,7 @@ int orc_rows(PROB_ARGS, int op, int64_t nrows, const int64_t *rows, int maxband,
                         t = conv_deriv(&P, Q->grad[b]) * Q->val[a];
                     } else {
                         t = 0.0;
-                        for (int k = 0; k < P.d; ++k) t += Q->grad[b][k] * Q->grad[a][k];
+                        t = diff_dot(&P, Q->grad[b], Q->grad[a]);
                     }
                     acc[box_offset(&P, mi, Q->lidx[b])] += s * t;
                 }
@@ -558,7 +577,7 @@ int orc_apply_rows(PROB_ARGS, int op, const double *x, int64_t nrows, const int6
                     for (int b = 0; b < Q->nloc; ++b)
                         for (int k = 0; k < P.d; ++k) gu[k] += x[Q->gidx[b]] * Q->grad[b][k];
                     double t = 0.0;
-                    for (int k = 0; k < P.d; ++k) t += gu[k] * Q->grad[a][k];
+                    t = diff_dot(&P, gu, Q->grad[a]);
                     acc += s * t;
                 }
             }
@@ -627,7 +646,7 @@ int orc_apply(PROB_ARGS, int op, const double *x, double *y, int nthreads)
                         for (int k = 0; k < P.d; ++k) gu[k] += x[Q->gidx[b]] * Q->grad[b][k];
                     for (int a = 0; a < Q->nloc; ++a) {
                         double t = 0.0;
-                        for (int k = 0; k < P.d; ++k) t += gu[k] * Q->grad[a][k];
+                        t = diff_dot(&P, gu, Q->grad[a]);
                         y[Q->gidx[a]] += s * t;
                     }
                 }
@@ -701,7 +720,7 @@ int orc_apply_elements(PROB_ARGS, int op, const double *x, int64_t nlist, const 
                         for (int k = 0; k < P.d; ++k) gu[k] += x[Q->gidx[b]] * Q->grad[b][k];
                     for (int a = 0; a < Q->nloc; ++a) {
                         double t = 0.0;
-                        for (int k = 0; k < P.d; ++k) t += gu[k] * Q->grad[a][k];
+                        t = diff_dot(&P, gu, Q->grad[a]);
                         y[Q->gidx[a]] += s * t;
                     }
                 }

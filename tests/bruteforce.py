@@ -31,7 +31,7 @@ def basis_1d(knots, p, x):
     return np.nan_to_num(V), np.nan_to_num(D)
 
 
-def dense_bruteforce(knots_list, p, ctrl, coef, op, conv_b=None):
+def dense_bruteforce(knots_list, p, ctrl, coef, op, conv_b=None, diff_A=None):
     """Dense mass (op=1, coefficient 1), stiffness (op=2) or convection
     (op=4: b . grad u tested with v, b = coefficient * conv_b) matrix."""
     d = len(knots_list)
@@ -72,7 +72,9 @@ def dense_bruteforce(knots_list, p, ctrl, coef, op, conv_b=None):
             gi = sum(Jinv[:, k, i][:, None] * Qder[k] for k in range(d))
             A += Qval.T @ ((w * a * np.abs(det) * b[i])[:, None] * gi)
         return A
-    C = (w * a * np.abs(det))[:, None, None] * np.einsum("qij,qkj->qik", Jinv, Jinv)
+    Ad = np.eye(d) if diff_A is None else np.asarray(diff_A, dtype=np.float64)
+    # K = sum_q (J^-T g_n) . A (J^-T g_m) = g_n . (J^-1 A J^-T) g_m
+    C = (w * a * np.abs(det))[:, None, None] * np.einsum("qij,jk,qlk->qil", Jinv, Ad, Jinv)
     A = np.zeros((Qval.shape[1],) * 2)
     for i in range(d):
         for j in range(d):
