@@ -14,8 +14,8 @@
  *     (Sec. 2, Example 1), discretised as the quadrature sum
  *     eq. (quadrature:1):
  *        M[m][n] = sum_x w(x) c(G(x)) |det J| phi_n phi_m
- *        K[m][n] = sum_x w(x) a(G(x)) |det J| (J^-T grad phi_n).(J^-T grad phi_m)
- *     with J_ik = dG_i/dxhat_k;
+ *        K[m][n] = sum_x w(x) a(G(x)) |det J| (J^-T grad phi_n).A (J^-T grad phi_m)
+ *     with J_ik = dG_i/dxhat_k and A a constant symmetric matrix (default I);
  *   - the convection form of the same example, the b . grad u term of the
  *     equation tested with v (d = 3, FP64, matrix-free apply only):
  *        B[m][n] = sum_x w(x) s(G(x)) |det J| (b . J^-T grad phi_n) phi_m
@@ -164,12 +164,21 @@ sf_status sf_patch_info(const sf_patch *patch, int64_t *ndof, int64_t *nnz, int6
 
 /* Coefficient of operator `op` (exactly one of SF_MASS, SF_STIFF, SF_CONV):
  * the reaction coefficient c for the mass form, the scalar diffusion a for
- * the stiffness form (Example 1 with A = a I), the scalar s of the
+ * the stiffness form (Example 1 with A = a A0, A0 from sf_patch_set_diffusion), the scalar s of the
  * convection velocity s(x) b.  For SF_COEF_CONST and SF_COEF_SINPROD
  * `params` is a host pointer to one double; for SF_COEF_QPVALUES it is a
  * device pointer to Q doubles, which must stay valid until the next
  * sf_patch_prepare.  Default: constant 1 for all three. */
 sf_status sf_patch_set_coef(sf_patch *patch, unsigned op, sf_coef_kind kind, const double *params);
+
+/* The constant symmetric diffusion matrix A of the stiffness form (Sec. 2,
+ * Example 1: the diffusion becomes a(x) A, a from sf_patch_set_coef): host
+ * pointer to the d(d+1)/2 entries of its upper triangle, row by row (d = 3:
+ * A11 A12 A13 A22 A23 A33).  Physical coordinates; the geometry step folds
+ * w a |det J| J^-1 A J^-T.  A positive definite A gives an elliptic form
+ * (not checked).  Default the identity.  Takes effect at the next
+ * sf_patch_prepare of SF_STIFF (the stiffness is unprepared until then). */
+sf_status sf_patch_set_diffusion(sf_patch *patch, const double *A);
 
 /* The constant vector b of the convection form (Sec. 2, Example 1: the
  * b . grad u term), host pointer to d doubles in physical coordinates;

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SF_OK", -1: "SF_EINVAL", -2: "SF_EKNOT", -3: "SF_EGEOM", -4:
 
 EXPORTED = ["sf_ctx_create", "sf_ctx_destroy", "sf_last_error", "sf_build_target", "sf_host_tables_1d",
             "sf_patch_create",
-            "sf_patch_info", "sf_patch_set_coef", "sf_patch_set_convection", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
+            "sf_patch_info", "sf_patch_set_coef", "sf_patch_set_convection", "sf_patch_set_diffusion", "sf_patch_quad_points", "sf_patch_eval", "sf_patch_prepare",
             "sf_patch_prepare_async", "sf_patch_geometry_check", "sf_csr_pattern", "sf_assemble", "sf_assemble_noalloc", "sf_apply", "sf_patch_destroy", "sf_batch_create",
             "sf_batch_offsets", "sf_batch_assemble", "sf_batch_apply", "sf_glue_map", "sf_batch_apply_glued",
             "sf_batch_destroy"]
@@ -63,6 +63,7 @@ def lib():
         "sf_patch_info": (st, [vp, i64p, i64p, i64p]),
         "sf_patch_set_coef": (st, [vp, ctypes.c_uint, ctypes.c_int, vp]),
         "sf_patch_set_convection": (st, [vp, vp]),
+        "sf_patch_set_diffusion": (st, [vp, vp]),
         "sf_patch_quad_points": (st, [vp, vp]),
         "sf_patch_eval": (st, [vp, vp, vp, vp]),
         "sf_patch_prepare": (st, [vp, ctypes.c_uint, ctypes.c_int]),
@@ -191,6 +192,12 @@ def sf_patch_set_coef(ctx, patch, op, kind, value=None, qp_values=None):
 def sf_patch_set_convection(ctx, patch, b):
     v = (ctypes.c_double * len(b))(*[float(t) for t in b])
     _check(lib().sf_patch_set_convection(patch, ctypes.cast(v, ctypes.c_void_p)), ctx)
+
+
+def sf_patch_set_diffusion(ctx, patch, A_upper):
+    """A_upper: the d(d+1)/2 upper-triangle entries of the symmetric A, row by row."""
+    v = (ctypes.c_double * len(A_upper))(*[float(t) for t in A_upper])
+    _check(lib().sf_patch_set_diffusion(patch, ctypes.cast(v, ctypes.c_void_p)), ctx)
 
 
 def sf_patch_quad_points(ctx, patch, xyz):

@@ -4,7 +4,8 @@
 // coefficient at the physical point G(x), and the folded quadrature
 // coefficients (Example 1 with A = a I):
 //   mass:      w c |det J|
-//   stiffness: w a |det J| (J^-1 J^-T)_ij, i <= j   (J_ik = dG_i/dxhat_k)
+//   stiffness: w a |det J| (J^-1 A J^-T)_ij, i <= j   (J_ik = dG_i/dxhat_k,
+//              A the constant symmetric diffusion matrix, the identity by default)
 //   convection: w s |det J| (J^-1 b)_k, k = 1..3 (b . grad u = (J^-1 b) . grad_hat u)
 #include <hip/hip_fp16.h>
 
@@ -69,9 +70,14 @@ __device__ __forceinline__ void pointwise_3d(const double G[3], const double J[3
     }
     if (o.c_stiff) {
         double s = wd * eval_coef(o.coef_stiff, G, 3, qlin);
+        // rows of J^-1 A: ai[j][k] = sum_l A_kl (J^-1)_jl (equal to J^-1 for A = I)
+        double ai[3][3];
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                ai[j][k] = o.adiff[3 * k] * inv[j][0] + o.adiff[3 * k + 1] * inv[j][1] + o.adiff[3 * k + 2] * inv[j][2];
         for (int i = 0; i < 3; ++i)
             for (int j = i; j < 3; ++j) {
-                double v = s * (inv[i][0] * inv[j][0] + inv[i][1] * inv[j][1] + inv[i][2] * inv[j][2]);
+                double v = s * (inv[i][0] * ai[j][0] + inv[i][1] * ai[j][1] + inv[i][2] * ai[j][2]);
                 const int c = sym_comp<3>(i, j);
                 int64_t idx = coef_index(3, 6, c, q0, q1, q2, Q0, Q1);
                 if (f32) store_coef<float>(o.c_stiff, idx, v); else store_coef<double>(o.c_stiff, idx, v);
@@ -323,8 +329,13 @@ __global__ void geom_small_kernel(PatchView pv, GeomOut o)
         constexpr int NC = DIM * (DIM + 1) / 2;
         for (int i = 0; i < DIM; ++i)
             for (int j = i; j < DIM; ++j) {
+                // (J^-1 A J^-T)_ij, A the symmetric diffusion matrix
                 double v = 0.0;
-                for (int k = 0; k < DIM; ++k) v += inv[i][k] * inv[j][k];
+                for (int k = 0; k < DIM; ++k) {
+                    double a = 0.0;
+                    for (int l = 0; l < DIM; ++l) a += o.adiff[3 * k + l] * inv[j][l];
+                    v += inv[i][k] * a;
+                }
                 int64_t idx = coef_index(DIM, NC, sym_comp<DIM>(i, j), q0, q1, 0, d0.Q, d1.Q);
                 if (f32) store_coef<float>(o.c_stiff, idx, s * v); else store_coef<double>(o.c_stiff, idx, s * v);
             }

@@ -114,6 +114,7 @@ struct GeomOut {
     double *c_conv;        // convection, FP64 in the layout of conv_coef_index (d = 3), or null
     Coef coef_mass, coef_stiff, coef_conv;
     double bconv[3];       // the convection vector b (scaled by coef_conv)
+    double adiff[9];       // the symmetric diffusion matrix A, row-major (stiffness: a(x) A)
     int *bad_det;          // device flag set to 1 if det J <= 0 somewhere, or null
     Prec prec;
     // evaluation of a discrete function u = sum_n u_n phi_n (Algorithm 3):

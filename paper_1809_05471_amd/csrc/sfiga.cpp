@@ -40,6 +40,7 @@ struct sf_patch {
     double *dctrl = nullptr;
     int *dflag = nullptr;
     Coef coef[2];                 // [0] mass, [1] stiffness
+    double adiff[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};   // diffusion matrix A of the stiffness form (a(x) A)
     // [op][storage: FP64, FP32, FP16 residual of the FP16 split]
     void *C[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     float *rs[2] = {nullptr, nullptr};   // [op] per-element reference and scale of the FP16 split
@@ -388,6 +389,24 @@ sf_status sf_patch_set_coef(sf_patch *p, unsigned op, sf_coef_kind kind, const d
     return SF_OK;
 }
 
+sf_status sf_patch_set_diffusion(sf_patch *p, const double *A)
+{
+    if (!p) return SF_EINVAL;
+    p->ctx->err.clear();
+    if (!A) return fail(p->ctx, SF_EINVAL, "null matrix");
+    double m[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int i = 0, t = 0; i < p->d; ++i)
+        for (int j = i; j < p->d; ++j, ++t) m[3 * i + j] = m[3 * j + i] = A[t];
+    // the relabelled patch of a tuned contraction order has the same
+    // physical coordinates, so the same A
+    for (sf_patch *q : {p, p->alt}) {
+        if (!q) continue;
+        for (int k = 0; k < 9; ++k) q->adiff[k] = m[k];
+        for (bool &r : q->ready[1]) r = false;
+    }
+    return SF_OK;
+}
+
 sf_status sf_patch_set_convection(sf_patch *p, const double *b)
 {
     if (!p) return SF_EINVAL;
@@ -454,6 +473,7 @@ static sf_status prepare_impl(sf_patch *p, unsigned ops, sf_precision prec, bool
     o.bad_det = p->dflag;
     o.coef_mass = p->coef[0];
     o.coef_stiff = p->coef[1];
+    for (int k = 0; k < 9; ++k) o.adiff[k] = p->adiff[k];
     auto alloc = [&](void **ptr, size_t bytes) -> sf_status {
         if (*ptr) return SF_OK;
         hipError_t e = hipMalloc(ptr, bytes);
@@ -733,6 +753,7 @@ static sf_status make_alt(sf_patch *p, int sh)
     a->assembly_only = true;
     a->coef[0] = p->coef[0];
     a->coef[1] = p->coef[1];
+    for (int k = 0; k < 9; ++k) a->adiff[k] = p->adiff[k];
     e = hipMalloc((void **)&p->tmpv, sizeof(double) * (size_t)p->view.nnz);
     if (e != hipSuccess) {
         p->tmpv = nullptr;
