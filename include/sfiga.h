@@ -108,7 +108,10 @@ typedef struct sf_batch sf_batch;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
  * borrowed from the caller (NULL = the legacy default stream); it must
- * outlive the context.  *out receives the handle. */
+ * outlive the context.  *out receives the handle.  Makes `device` the calling
+ * host thread's current HIP device (hipSetDevice); the library does not
+ * switch devices afterwards, so calls on the context and its patches and
+ * batches must be made while that device is current. */
 sf_status sf_ctx_create(int device, void *hip_stream, sf_ctx **out);
 
 /* Destroy a context.  All patches and batches created on it must have been
