@@ -118,12 +118,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched", "order", "conv"], default="large",
+    ap.add_argument("--workload", choices=["large", "single", "sweep", "batched", "order", "conv", "glued"], default="large",
                     help="large: d=3 128^3 order 6, geometry + pattern + assembly + 100 applies per step (the "
                          "headline line); single: 48^3 order 4 with one apply; sweep: matrix-free apply at "
                          "N = 126^3 for orders 2..9; batched: 512 patches; order: stiffness assembly of "
                          "anisotropic patches in the given and the relabelled contraction order; conv: "
-                         "matrix-free convection product (FP64) at 128^3 order 6 and N = 126^3 for orders 2..9")
+                         "matrix-free convection product (FP64) at 128^3 order 6 and N = 126^3 for orders 2..9; "
+                         "glued: stiffness product of the unit cube as 2 x 2 x 2 glued patches of 64^3 elements, "
+                         "order 6, against the same patches unglued")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "fp16"], default=None,
                     help="precision of the timed step (default fp64; sweep and batched: see their help)")
     ap.add_argument("--mixed-steps", type=int, default=3,
@@ -160,6 +162,8 @@ def main():
         return run_order(args)
     if args.workload == "conv":
         return run_conv(args)
+    if args.workload == "glued":
+        return run_glued(args)
     return run_patch(args)
 
 
@@ -518,6 +522,78 @@ def run_conv(args):
         sf.sf_patch_destroy(h)
         del x, y
         torch.cuda.empty_cache()
+    sf.sf_ctx_destroy(ctx)
+
+
+def run_glued(args):
+    """The unit cube as 2 x 2 x 2 patches of 64^3 elements at order 6 (each
+    the identity map of its octant), glued at their faces: y = sum_b R_b^T
+    K_b R_b x (sf_batch_apply_glued), timed beside sf_batch_apply on the
+    same patches (the gather and scatter are the difference).  FP64 unless
+    --prec fp32; on a side stream (captured graphs)."""
+    import torch
+
+    import paper_1809_05471_amd as sf
+    from paper_1809_05471_amd import inputs
+    prec = sf.SF_FP32 if args.prec == "fp32" else sf.SF_FP64
+    Kp, p = 64, 6
+    stream = torch.cuda.Stream()
+    ctx = sf.sf_ctx_create(0, stream.cuda_stream)
+    kn = inputs.open_uniform_knots(Kp, p)
+    g1 = inputs.greville(kn, p) * 0.5
+    hs, nf = [], []
+    with torch.cuda.stream(stream):
+        for c in np.ndindex(2, 2, 2):
+            axes = [g1 + 0.5 * c[k] for k in range(3)]
+            grid = np.meshgrid(*axes[::-1], indexing="ij")
+            ctrl = np.stack([grid[2 - k].ravel() for k in range(3)], axis=1)
+            h = sf.sf_patch_create(ctx, 3, p, [kn] * 3, ctrl)
+            sf.sf_patch_set_coef(ctx, h, sf.SF_STIFF, sf.SF_COEF_SINPROD, 0.5)
+            sf.sf_patch_prepare(ctx, h, sf.SF_STIFF, prec)
+            hs.append(h)
+            nf.append([Kp + p - 1] * 3)
+        ids = {c: i for i, c in enumerate(np.ndindex(2, 2, 2))}
+        ifc = []
+        for c, i in ids.items():
+            for k in range(3):
+                if c[k] == 0:
+                    q = list(c)
+                    q[k] = 1
+                    ifc.append((i, 2 * k + 1, ids[tuple(q)], 2 * k))
+        m, ng = sf.sf_glue_map(3, nf, ifc)
+        bt = sf.sf_batch_create(ctx, hs)
+        nloc = len(m)
+        dmap = torch.as_tensor(m).cuda()
+        x = torch.as_tensor(inputs.random_vector(ng, 0)).cuda()
+        y = torch.empty(ng, dtype=torch.float64, device="cuda")
+        xl = torch.as_tensor(inputs.random_vector(nloc, 0)).cuda()
+        yl = torch.empty(nloc, dtype=torch.float64, device="cuda")
+        out = {}
+        for name, call in (("glued", lambda: sf.sf_batch_apply_glued(ctx, bt, sf.SF_STIFF, prec, dmap, ng, x, y)),
+                           ("unglued", lambda: sf.sf_batch_apply(ctx, bt, sf.SF_STIFF, prec, xl, yl))):
+            for _ in range(max(args.warmup, 1)):
+                call()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                call()
+            e1.record(stream)
+            e1.synchronize()
+            out[name] = e0.elapsed_time(e1) / args.steps
+        Q = 8 * (Kp * p) ** 3
+        byts = Q * coef_bytes_per_point("fp64" if prec == sf.SF_FP64 else "fp32", p=p) + 16 * nloc
+        ms = out["glued"]
+        print(json.dumps({
+            "metric": "matrix-free apply GDoF/s", "value": ng / (ms * 1e-3) / 1e9, "unit": "GDoF/s", "ms": ms,
+            "dtype": "f64" if prec == sf.SF_FP64 else "f32",
+            "config": {"workload": f"d3_glued_2x2x2_patches_{Kp}^3_p{p}_stiffness_apply", "order": p,
+                       "ndof_global": ng, "ndof_local": nloc, "nquad": Q},
+            "unglued_batch_apply_ms": out["unglued"],
+            "roofline": {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "algorithmic_bytes": byts}}), flush=True)
+        sf.sf_batch_destroy(bt)
+        for h in hs:
+            sf.sf_patch_destroy(h)
     sf.sf_ctx_destroy(ctx)
 
 

@@ -881,6 +881,44 @@ sf_status sf_assemble_noalloc(sf_patch *p, unsigned ops, sf_precision prec, doub
     return SF_OK;
 }
 
+// Apply autotuner: element layers per workgroup of the d = 3 apply, timed
+// on the patch into y (which the caller's launch then rewrites); once per
+// (operator, precision).  Outside any graph capture.
+static sf_status tune_apply_lz(sf_patch *p, int oi, int pi, const void *C, bool tiled, const double *x, double *y)
+{
+    const Prec pr = apply_prec(pi);
+    hipStream_t s = p->ctx->stream;
+    p->tune_lz[oi][pi] = 0;
+    if (p->d == 3) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, 0, p->rs[oi], tiled);   // warm-up
+        float best = 1e30f;
+        for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            if (e != hipSuccess || lz > p->view.dir[2].K) break;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
+                float t = 0.f;
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz, p->rs[oi], tiled);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+                ms = t < ms ? t : ms;
+            }
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                p->tune_lz[oi][pi] = lz;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
+    }
+    return SF_OK;
+}
+
 sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x, double *y)
 {
     if (!p) return SF_EINVAL;
@@ -908,36 +946,8 @@ sf_status sf_apply(sf_patch *p, unsigned op, sf_precision prec, const double *x,
     const void *C = tiled ? p->CA[oi][geom_storage(pi)] : p->C[oi][cidx(pi)];
     hipStream_t s = p->ctx->stream;
     if (p->tune_lz[oi][pi] < 0) {
-        // autotuner: element layers per workgroup, timed on this patch into y
-        // (rewritten by the launch below); once per (operator, precision)
-        p->tune_lz[oi][pi] = 0;
-        if (p->d == 3) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            hipError_t e = hipEventCreate(&e0);
-            if (e == hipSuccess) e = hipEventCreate(&e1);
-            if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, 0, p->rs[oi], tiled);   // warm-up
-            float best = 1e30f;
-            for (int lz : {1, 2, 3, 4, 6, 8, 12, 16}) {
-                if (e != hipSuccess || lz > p->view.dir[2].K) break;
-                float ms = 1e30f;
-                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // best of two
-                    float t = 0.f;
-                    e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_apply(p->view, oi + 1, pr, C, x, y, s, lz, p->rs[oi], tiled);
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-                    ms = t < ms ? t : ms;
-                }
-                if (e == hipSuccess && ms < best) {
-                    best = ms;
-                    p->tune_lz[oi][pi] = lz;
-                }
-            }
-            if (e0) (void)hipEventDestroy(e0);
-            if (e1) (void)hipEventDestroy(e1);
-            if (e != hipSuccess) return hip_fail(p->ctx, e, "apply autotuning");
-        }
+        sf_status st2 = tune_apply_lz(p, oi, pi, C, tiled, x, y);
+        if (st2 != SF_OK) return st2;
     }
     hipError_t e = launch_apply(p->view, oi + 1, pr, C, x, y, s, p->tune_lz[oi][pi], p->rs[oi], tiled);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "apply kernel");
@@ -1010,11 +1020,24 @@ struct BatchIO {
     double *y = nullptr;
 };
 
+// A d = 3 patch whose own apply launch fills the chip many times over (at
+// least 8 workgroups per compute unit) gains nothing from the shared
+// persistent grid, and its single-patch kernel reads the tiled coefficient
+// copy where the patch has one (8 patches of 64^3 elements at order 6, FP64:
+// 8.87 ms in the persistent kernel).
+static bool apply_alone(const sf_patch *p, int oi, int pi)
+{
+    if (p->d != 3 || pi == 3 || !p->CA[oi][geom_storage(pi)]) return false;
+    int gx, gy, gz, LZ;
+    apply_blocks(p->view, 0, gx, gy, gz, LZ);
+    return (int64_t)gx * gy * gz >= 8 * 256;
+}
+
 static bool persistent_ok(const sf_patch *p, int kernel, int oi, int pi)
 {
     if (kernel == KROWPTR || kernel == KCOLIND) return true;
     if (p->d != 3) return false;
-    if (kernel == KAPPLY) return true;
+    if (kernel == KAPPLY) return !apply_alone(p, oi, pi);
     return assemble_single_chunk(p->view, oi + 1, asm_prec(pi), p->ws_bytes);
 }
 
@@ -1204,6 +1227,15 @@ static sf_status plan_call(sf_batch *b, int kind, unsigned ops, int pi, const Ba
             if (st != SF_OK) return st;
             plan.push_back(Plan{KAPPLY, P, oi, param, mult, {}});
         }
+        // patches applied alone: their layers per workgroup, tuned on their
+        // share of the call's vectors
+        for (size_t i = 0; i < b->patches.size(); ++i) {
+            sf_patch *p = b->patches[i];
+            if (!apply_alone(p, oi, pi) || p->tune_lz[oi][pi] >= 0) continue;
+            const int64_t r0 = b->row_off[i];
+            sf_status st = tune_apply_lz(p, oi, pi, p->CA[oi][geom_storage(pi)], true, io_in.x + r0, io_in.y + r0);
+            if (st != SF_OK) return st;
+        }
     }
     for (Plan &pl : plan) {
         sf_status st = prepare_launch(b, pl, pi, io_in);
@@ -1225,7 +1257,8 @@ static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const 
         hipError_t e = launch_kernel(pl.kernel, pl.tl, pl.P, pl.oi, pi, b->ncu * pl.mult, s);
         if (e != hipSuccess) return hip_fail(b->ctx, e, "batched kernel");
     }
-    // patches the persistent kernels do not take (d < 3, or assembled in chunks)
+    // patches the persistent kernels do not take (d < 3, assembled in chunks,
+    // or applied alone)
     for (size_t i = 0; i < b->patches.size(); ++i) {
         sf_patch *p = b->patches[i];
         const int64_t r0 = b->row_off[i], z0 = b->nnz_off[i];
@@ -1239,8 +1272,11 @@ static sf_status record_call(sf_batch *b, int kind, unsigned ops, int pi, const 
                 double *dst = io_in.vals[oi] + z0;
                 e = launch_assemble(p->view, oi + 1, asm_prec(pi), p->C[oi][cidx(pi)], dst, p->ws, p->ws_bytes, s);
             } else {
-                e = launch_apply(p->view, oi + 1, apply_prec(pi), p->C[oi][cidx(pi)], io_in.x + r0, io_in.y + r0, s, 0,
-                                 p->rs[oi]);
+                const bool tiled = apply_alone(p, oi, pi);
+                const void *C = tiled ? p->CA[oi][geom_storage(pi)] : p->C[oi][cidx(pi)];
+                const int lz = p->tune_lz[oi][pi] > 0 ? p->tune_lz[oi][pi] : 0;
+                e = launch_apply(p->view, oi + 1, apply_prec(pi), C, io_in.x + r0, io_in.y + r0, s, lz, p->rs[oi],
+                                 tiled);
             }
             if (e != hipSuccess) return hip_fail(b->ctx, e, "per-patch kernel");
         }

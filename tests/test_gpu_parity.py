@@ -846,3 +846,49 @@ def test_contraction_order(monkeypatch, policy, K, p):
         g.prepare(sf.SF_STIFF)
         v = g.assemble(sf.SF_STIFF)
         assert err_A(v, v_o) <= TOL64
+
+
+@pytest.mark.parametrize("prec,tol", [(sf.SF_FP64, TOL64), (sf.SF_FP32, TOL32)])
+def test_batched_apply_with_a_patch_applied_alone(prec, tol):
+    """A batch patch whose own apply launch fills the chip (32 x 32 x 64
+    elements at order 4, about 2k workgroups) runs its single-patch kernel on
+    the tiled coefficient copy inside the captured batch call; the small
+    patch beside it stays in the persistent kernel.  Sampled rows of the
+    large patch and the whole small one against the oracle, on two calls."""
+    import torch
+    from tests.gpu_util import side_ctx
+    c, stream = side_ctx()
+    specs = [((32, 32, 64), 4, 3), ((4, 5, 3), 3, 4)]
+    patches, probs, xs = [], [], []
+    with torch.cuda.stream(stream):
+        try:
+            for K, p, seed in specs:
+                kn, ctrl = inputs.perturbed_geometry(K, p, seed=seed, amp=0.05)
+                g = GpuPatch(kn, p, ctrl, ("sinprod", 0.5), context=c)
+                g.prepare(sf.SF_STIFF, prec)
+                patches.append(g)
+                probs.append(oracle.Problem(kn, p, ctrl, ("sinprod", 0.5)))
+                xs.append(inputs.random_vector(g.N, seed))
+            bt = sf.sf_batch_create(c, [g.h for g in patches])
+            ro, _ = sf.sf_batch_offsets(c, bt, 2)
+            x = torch.as_tensor(np.concatenate(xs)).cuda()
+            y = torch.empty(int(ro[-1]), dtype=torch.float64, device="cuda")
+            rng = np.random.default_rng(5)
+            rows = sample_rows(probs[0].nfun, rng, nrandom=8, coarse=True, p=4, band="cross")
+            yref0 = probs[0].apply_rows_by_elements(oracle.STIFF, xs[0], rows)
+            den0 = max(float(np.abs(v) @ np.abs(xs[0][cc])) for cc, v in probs[0].rows(oracle.STIFF, rows))
+            rp, ci, v = probs[1].assemble(oracle.STIFF)
+            A1 = oracle.csr_to_dense(rp, ci, v, probs[1].N)
+            for rep in range(2):
+                y.fill_(float("nan"))
+                sf.sf_batch_apply(c, bt, sf.SF_STIFF, prec, x, y)
+                stream.synchronize()
+                yn = y.cpu().numpy()
+                e0 = float(np.abs(yn[ro[0]:ro[1]][rows] - yref0).max() / den0)
+                e1 = err_y(yn[ro[1]:ro[2]], A1 @ xs[1], np.abs(A1) @ np.abs(xs[1]))
+                record("err_y", prec, max(e0, e1))
+                assert e0 <= tol and e1 <= tol, (rep, e0, e1)
+            sf.sf_batch_destroy(bt)
+        finally:
+            for g in patches:
+                g.close()
