@@ -47,16 +47,16 @@ struct ConvTile {
     // whole wavefronts per element: fewer LDS reads per multiply-add, but
     // idle lanes and strided coefficient loads.  Measured per order at
     // N = 126^3 against one item per point: 0.84 / 0.87 ms at order 4, 5.96 /
-    // 6.10 at 7, 21.9 / 24.8 at 9; slower at 2, 5, 6 and 8 (order 6: 4.11 /
-    // 3.06 ms, order 8: 13.0 / 10.6), equal at 3.
-    static constexpr bool ROWF1 = P == 4 || P == 7 || P == 9;
+    // 6.10 at 7, 21.9 / 24.8 at 9, and at 8 (two elements per tile side, with
+    // ROWB) 9.79 against 10.6 with one element and one item per point; slower
+    // at 2, 5 and 6 (order 6: 4.11 / 3.06 ms), equal at 3.
+    static constexpr bool ROWF1 = P == 4 || P >= 7;
     // ROWB: backward directions 1 and 2 per element row as well, each item
     // adding its p sums into the shared rows with LDS atomics.  Measured at
     // N = 126^3 against the gather per function: 0.110 / 0.126 ms at order 2,
     // 0.41 / 0.43 at 3, 0.80 / 0.85 at 4, 3.07 / 3.10 at 6, 5.68 / 5.96 at 7,
-    // equal at 5; slower at 8 (10.84 / 10.74) and at 9, where it spills
-    // (26.4 / 22.0 ms).
-    static constexpr bool ROWB = P <= 7;
+    // equal at 5; at 9 it spills (26.4 / 22.0 ms).
+    static constexpr bool ROWB = P <= 8;
     static constexpr int R = P * T, R64 = (R + 63) / 64 * 64;
     static constexpr int NIT = (E * R64 + NT - 1) / NT;  // element rows per thread
     // the same for direction 2 (element l2, plane g3, function column lx)

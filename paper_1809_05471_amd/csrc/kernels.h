@@ -73,9 +73,9 @@ __host__ __device__ inline int64_t apply_coef_size(int ncomp, int P, int K0, int
 }
 
 // Elements per tile side of the convection kernel (d = 3): about 16
-// quadrature points per side up to order 6, two elements at order 7 and one
-// at orders 8 and 9 (measured fastest; LDS at most about 48 KiB).
-__host__ __device__ constexpr int conv_tile_elems(int P) { return P <= 6 ? (16 + P - 1) / P : (P == 7 ? 2 : 1); }
+// quadrature points per side up to order 6, two elements at orders 7 and 8
+// and one at order 9 (measured fastest; LDS at most about 63 KiB).
+__host__ __device__ constexpr int conv_tile_elems(int P) { return P <= 6 ? (16 + P - 1) / P : (P <= 8 ? 2 : 1); }
 
 // Convection coefficient layout (d = 3): tiles of T x T quadrature columns
 // (T = conv_tile_elems(P) * P; direction 1 fastest), per tile and quadrature
